@@ -1,0 +1,144 @@
+"""Exact product blocks, best approximation and acceptance (oracle).
+
+What the product path must compute has a plain definition: for every farfield
+leaf tau x sigma of the block-cluster tree, the best approximation at relative
+Frobenius tolerance eps of the exact block (A_H B_H)[tau, sigma] (the epsilon-rank
+notion of the numerical-examples section; Eckart-Young gives the optimum), and
+for every nearfield leaf the exact block itself (evaluate() in Algorithm 4).
+
+Two ways of getting exact blocks, both written out from that definition:
+  * brute force: densify A_H and B_H, one GEMM (small n only);
+  * strips: D[tau, sigma] = A_H[tau, :] @ B_H[:, sigma] with both strips densified
+    (any n; used on sampled blocks).
+"""
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from .assemble import eps_rank, truncate
+from .hmatrix import HMatrix, KIND_F
+
+
+class StripIndex:
+    """Vectorised leaf lookup for strip densification of large H-matrices."""
+
+    def __init__(self, H: HMatrix):
+        self.H = H
+        self.r0 = np.array([b.r0 for b in H.leaves], dtype=np.int64)
+        self.r1 = self.r0 + np.array([b.m for b in H.leaves], dtype=np.int64)
+        self.c0 = np.array([b.c0 for b in H.leaves], dtype=np.int64)
+        self.c1 = self.c0 + np.array([b.n for b in H.leaves], dtype=np.int64)
+
+    def row_strip(self, a: int, b: int) -> np.ndarray:
+        S = np.zeros((b - a, self.H.n))
+        for i in np.nonzero((self.r0 < b) & (self.r1 > a))[0]:
+            lf = self.H.leaves[i]
+            lo, hi = max(a, lf.r0), min(b, lf.r0 + lf.m)
+            if lf.kind == KIND_F:
+                S[lo - a:hi - a, lf.c0:lf.c0 + lf.n] = lf.L[lo - lf.r0:hi - lf.r0] @ lf.R.T
+            else:
+                S[lo - a:hi - a, lf.c0:lf.c0 + lf.n] = lf.D[lo - lf.r0:hi - lf.r0]
+        return S
+
+    def col_strip(self, a: int, b: int) -> np.ndarray:
+        S = np.zeros((self.H.n, b - a))
+        for i in np.nonzero((self.c0 < b) & (self.c1 > a))[0]:
+            lf = self.H.leaves[i]
+            lo, hi = max(a, lf.c0), min(b, lf.c0 + lf.n)
+            if lf.kind == KIND_F:
+                S[lf.r0:lf.r0 + lf.m, lo - a:hi - a] = lf.L @ lf.R[lo - lf.c0:hi - lf.c0].T
+            else:
+                S[lf.r0:lf.r0 + lf.m, lo - a:hi - a] = lf.D[:, lo - lf.c0:hi - lf.c0]
+        return S
+
+
+def exact_block_strips(ia: StripIndex, ib: StripIndex, r0, m, c0, n) -> np.ndarray:
+    """(A_H B_H)[r0:r0+m, c0:c0+n] = A_H[rows, :] @ B_H[:, cols]."""
+    return ia.row_strip(r0, r0 + m) @ ib.col_strip(c0, c0 + n)
+
+
+def brute_force_product(A: HMatrix, B: HMatrix) -> np.ndarray:
+    """Dense A_H @ B_H in cluster order."""
+    return A.to_dense(1) @ B.to_dense(1)
+
+
+def best_approximation(D: np.ndarray, eps: float):
+    """Eckart-Young best approximation of D at relative Frobenius tolerance eps."""
+    return truncate(D, eps)
+
+
+@dataclass
+class BlockCheck:
+    kind: int
+    err: float  # relative Frobenius error of the candidate
+    rank: int  # candidate rank (farfield)
+    kstar: int  # oracle's epsilon-rank (farfield)
+    ok: bool
+
+
+def check_block(D: np.ndarray, kind: int, eps: float, U=None, V=None, Dc=None,
+                err_factor: float = 1.01, rank_slack: int = 2, near_tol: float = 1e-12) -> BlockCheck:
+    """Acceptance of one candidate block against the exact block D.
+
+    Farfield: ||D - U V^T||_F <= err_factor * eps * ||D||_F and
+              rank <= k* + rank_slack, with k* the epsilon-rank of D.
+    Nearfield: ||D - Dc||_F <= near_tol * ||D||_F.
+    """
+    nd = float(np.linalg.norm(D))
+    if kind == KIND_F:
+        s = np.linalg.svd(D, compute_uv=False) if D.size else np.zeros(0)
+        kstar = eps_rank(s, eps)
+        approx = U @ V.T if U.shape[1] else np.zeros_like(D)
+        e = float(np.linalg.norm(D - approx))
+        rel = e / nd if nd > 0 else (0.0 if e == 0.0 else np.inf)
+        ok = (e <= err_factor * eps * nd) and (U.shape[1] <= kstar + rank_slack)
+        return BlockCheck(kind, rel, U.shape[1], kstar, ok)
+    e = float(np.linalg.norm(D - Dc))
+    rel = e / nd if nd > 0 else (0.0 if e == 0.0 else np.inf)
+    return BlockCheck(kind, rel, -1, -1, e <= near_tol * nd or e == 0.0)
+
+
+def blockwise_best_product(A: HMatrix, B: HMatrix, eps: float) -> HMatrix:
+    """The whole target: blockwise best approximation of A_H B_H on B's partition
+    (brute force; small n)."""
+    D = brute_force_product(A, B)
+    C = HMatrix(n=A.n, perm=A.perm.copy())
+    from .hmatrix import Leaf, KIND_N  # local import keeps the public surface small
+    for lf in B.leaves:
+        blk = D[lf.r0:lf.r0 + lf.m, lf.c0:lf.c0 + lf.n]
+        if lf.kind == KIND_F:
+            L, R, _, _ = truncate(blk, eps)
+            C.leaves.append(Leaf(lf.r0, lf.m, lf.c0, lf.n, KIND_F, L=L, R=R, level=lf.level))
+        else:
+            C.leaves.append(Leaf(lf.r0, lf.m, lf.c0, lf.n, KIND_N, D=blk.copy(), level=lf.level))
+    return C
+
+
+def global_error_estimate(C: HMatrix, A: HMatrix, B: HMatrix, iters: int = 10, size: int = 100,
+                          seed: int = 0):
+    """Frobenius-norm estimate of C - A B by subspace iteration on
+    v -> C v - A (B v) (the error estimator of the numerical-examples section).
+    Returns (estimate of ||C - AB||_F, estimate of ||AB||_F)."""
+    rng = np.random.default_rng(seed)
+    n = A.n
+    size = min(size, n)
+
+    def err_op(X):
+        return C.matvec(X) - A.matvec(B.matvec(X))
+
+    def err_opT(X):
+        return C.rmatvec(X) - B.rmatvec(A.rmatvec(X))
+
+    X = rng.standard_normal((n, size))
+    for _ in range(iters):
+        Y, _ = np.linalg.qr(err_op(X))
+        X, _ = np.linalg.qr(err_opT(Y))
+    Y = err_op(X)
+    est_err = float(np.linalg.norm(Y))
+    Xp = rng.standard_normal((n, size))
+    for _ in range(iters):
+        Yp, _ = np.linalg.qr(A.matvec(B.matvec(Xp)))
+        Xp, _ = np.linalg.qr(B.rmatvec(A.rmatvec(Yp)))
+    est_norm = float(np.linalg.norm(A.matvec(B.matvec(Xp))))
+    return est_err, est_norm
