@@ -1,0 +1,322 @@
+/*
+ * hmat.h -- C ABI of the MI355X hierarchical-matrix product library.
+ *
+ * The library computes the product C = A B of two H-matrices that live on one
+ * block-cluster tree and, for every admissible (farfield) leaf tau x sigma of
+ * that tree, stores the best approximation at relative Frobenius tolerance eps
+ * of the exact block (A B)[tau, sigma]; inadmissible (nearfield) leaves of C
+ * hold the exact dense block. This is the product of Doelz, Harbrecht and
+ * Multerer, "On the best approximation of the hierarchical matrix product":
+ * sum-expressions (Def. 3.1) built by restriction (Algorithm 3) inside the
+ * recursive product (Algorithm 4), compressed by the blocked randomized scheme
+ * (Section 4, randomized low-rank approximation) that touches each sum only
+ * through its products with blocks of vectors (the sum-expression-times-vector
+ * identity ending Section 3).
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns an hmat_status; HMAT_OK is 0. On failure a message
+ *    is available from hmat_last_error() (thread-local, valid until the next
+ *    call on that thread). No C++ exception crosses this interface.
+ *  - Pointers documented as "host" are CPU memory owned by the caller; the
+ *    library copies what it needs before returning and never keeps them.
+ *  - Handles (hmat_tree, hmat, hmat_rank_model) are owned by the caller and
+ *    released with the matching *_destroy call. An hmat keeps a reference to
+ *    its tree, so a tree may be destroyed while matrices built on it live.
+ *  - Positions: a tree orders the points so that every cluster is a contiguous
+ *    range of positions ("cluster order"); perm[pos] is the original index of
+ *    the point at that position.
+ *  - Dense matrices exchanged with the caller are column-major with a leading
+ *    dimension argument.
+ *  - All device work runs on the HIP stream given in hmat_opts.stream (the
+ *    null stream when 0); entry points that return data to the host
+ *    synchronise that stream before returning.
+ *  - Errors are never swallowed: a call either completes its whole job or
+ *    returns a non-zero status (HMAT_ERR_NOT_CONVERGED additionally returns a
+ *    usable result, see hmat_multiply).
+ */
+#ifndef HMAT_H
+#define HMAT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hmat_status;
+enum {
+  HMAT_OK = 0,
+  HMAT_ERR_ARG = 1,            /* invalid argument (size, tolerance, null pointer, NaN point) */
+  HMAT_ERR_TREE_MISMATCH = 2,  /* factors do not share one block-cluster tree */
+  HMAT_ERR_NOT_CONVERGED = 3,  /* some farfield blocks exhausted the growth budget */
+  HMAT_ERR_DEVICE = 4,         /* HIP runtime error */
+  HMAT_ERR_OOM = 5,            /* device allocation failed */
+  HMAT_ERR_INTERNAL = 6
+};
+
+typedef struct hmat_tree_s* hmat_tree;
+typedef struct hmat_s* hmat;
+typedef struct hmat_rank_model_s* hmat_rank_model;
+
+/* Last error message of the calling thread (never NULL). */
+const char* hmat_last_error(void);
+
+/* Library version string. */
+const char* hmat_version(void);
+
+/*
+ * Device allocator hook. When set, every device allocation of the library goes
+ * through alloc(bytes, ctx) and free(ptr, ctx) (for instance a framework's
+ * caching allocator); when reset with NULL functions, hipMalloc/hipFree are
+ * used. Set it before creating handles and keep it alive while they live.
+ */
+hmat_status hmat_set_allocator(void* (*alloc_fn)(size_t bytes, void* ctx),
+                               void (*free_fn)(void* ptr, void* ctx), void* ctx);
+
+/* ------------------------------------------------------------------------ */
+/* Cluster tree and block-cluster tree (Section 2: Def. 2.2, Def. 2.3,       */
+/* Algorithm 1).                                                             */
+/* ------------------------------------------------------------------------ */
+
+enum { HMAT_SPLIT_MIDPOINT = 0, HMAT_SPLIT_MEDIAN = 1 };
+
+/*
+ * Builds the cluster tree of n points and the block-cluster tree on it.
+ *  xyz        host, n x 3 row-major float64 coordinates (copied).
+ *  leaf_size  a cluster with at most leaf_size points is a leaf (>= 1).
+ *  eta        admissibility: dist > 0 and max(diam tau, diam sigma) <= eta*dist,
+ *             with diam/dist taken on tight axis-aligned bounding boxes (> 0).
+ *  split      HMAT_SPLIT_MIDPOINT: halve the longest box edge (ties to the
+ *             lowest axis) at its midpoint, points <= mid to the first son;
+ *             HMAT_SPLIT_MEDIAN: first floor(#tau/2) points after a stable
+ *             sort along that edge. A cluster whose box has zero extent, or
+ *             whose midpoint cut would leave a son empty, stays a leaf.
+ *  out        receives the new tree handle.
+ * Sons of a block are tau' x sigma' in tau'-major order (Algorithm 1).
+ * Errors: HMAT_ERR_ARG for n < 1, leaf_size < 1, eta <= 0 or not finite, a
+ * non-finite coordinate, an unknown split or a NULL pointer.
+ */
+hmat_status hmat_build_tree(const double* xyz, int64_t n, int32_t leaf_size, double eta,
+                            int32_t split, hmat_tree* out);
+hmat_status hmat_tree_destroy(hmat_tree t);
+
+typedef struct {
+  int64_t n;
+  int32_t leaf_size;
+  int32_t split;
+  double eta;
+  int32_t depth;       /* depth of the block-cluster tree */
+  int32_t n_clusters;
+  int64_t n_blocks;    /* all blocks, inner ones included */
+  int64_t n_far;       /* admissible leaves (F) */
+  int64_t n_near;      /* inadmissible leaves (N) */
+  int32_t csp;         /* sparsity constant: max blocks per cluster (row or column) */
+} hmat_tree_info_t;
+
+hmat_status hmat_tree_info(hmat_tree t, hmat_tree_info_t* out);
+/* perm: host int32[n], perm[pos] = original index. */
+hmat_status hmat_tree_perm(hmat_tree t, int32_t* perm);
+/* Clusters in breadth-first order; each output is host int32[n_clusters]. */
+hmat_status hmat_tree_clusters(hmat_tree t, int32_t* begin, int32_t* size, int32_t* parent,
+                               int32_t* level);
+/* Blocks in breadth-first order; each output host int32[n_blocks]; kind is
+ * 0 = inner, 1 = farfield leaf (F), 2 = nearfield leaf (N). */
+hmat_status hmat_tree_blocks(hmat_tree t, int32_t* tau, int32_t* sigma, int32_t* level,
+                             int32_t* kind);
+
+/* ------------------------------------------------------------------------ */
+/* Options and statistics                                                   */
+/* ------------------------------------------------------------------------ */
+
+enum { HMAT_FP64 = 0, HMAT_FP32_APPLY = 1, HMAT_BF16_SKETCH = 2 };
+enum { HMAT_RANK_ADAPTIVE = 0, HMAT_RANK_PREDICT = 1 };
+
+typedef struct {
+  double t_total;      /* seconds, entry to completion (stream synchronised) */
+  double t_plan;       /* host planning of the work lists */
+  double t_restrict;   /* creation of low-rank terms (Algorithm 3 products) */
+  double t_sketch;     /* range finding incl. probes and growth rounds */
+  double t_project;    /* projection passes */
+  double t_core;       /* orthogonalisation, core SVD, truncation, output */
+  double t_near;       /* nearfield evaluation */
+  double t_predict;    /* rank-predictor inference */
+  double flops_alg;    /* algorithmic flops of the passes actually run */
+  double bytes_alg;    /* algorithmic operand bytes of the passes actually run */
+  int64_t n_far, n_near;
+  int64_t n_growth_rounds;   /* total growth rounds over all levels */
+  int64_t n_grown_blocks;    /* block-rounds that needed growth */
+  int64_t n_not_converged;
+  int64_t n_fallback;        /* learned mode: blocks whose prediction failed the check */
+  int64_t sketch_columns;    /* sum over farfield blocks of sketch columns used */
+  int64_t peak_bytes;        /* peak device workspace of the call */
+  int32_t n_batches;         /* subtree batches the product was split into */
+  int32_t rank_hist[65];     /* output ranks; index 64 counts ranks >= 64 */
+} hmat_stats;
+
+typedef struct {
+  int32_t precision;   /* HMAT_FP64 (default), HMAT_FP32_APPLY, HMAT_BF16_SKETCH */
+  int32_t rank_mode;   /* HMAT_RANK_ADAPTIVE (default) or HMAT_RANK_PREDICT */
+  int32_t b0;          /* initial sketch width (default 8) */
+  int32_t growth;      /* columns added per growth round (default 8) */
+  int32_t probes;      /* probe columns of the a-posteriori check (default 8) */
+  int32_t max_growth;  /* growth rounds before HMAT_ERR_NOT_CONVERGED (default 6) */
+  int32_t p_l;         /* oversampling added to a predicted rank (default 3) */
+  int32_t reserved;
+  double delta;        /* residual target: E <= delta * eps * ||S||_F (default 0.05) */
+  uint64_t seed;       /* random stream of the sketches (default 0x5eed) */
+  void* stream;        /* hipStream_t (0 = null stream) */
+  hmat_rank_model rank_model;  /* required for HMAT_RANK_PREDICT */
+  hmat_stats* stats;   /* optional output */
+  int64_t workspace_limit;     /* bytes of device workspace per subtree batch (0 = auto) */
+} hmat_opts;
+
+/* Fills *o with the defaults listed above. */
+void hmat_opts_default(hmat_opts* o);
+
+/* ------------------------------------------------------------------------ */
+/* Assembly of kernel matrices                                              */
+/* ------------------------------------------------------------------------ */
+
+enum { HMAT_KERNEL_LAPLACE_4PI = 0, HMAT_KERNEL_INV_DIST = 1, HMAT_KERNEL_EXP = 2 };
+
+typedef struct {
+  int32_t kind;   /* 1/(4 pi r), 1/r or exp(-r) of r = ||x_i - x_j||_2 */
+  int32_t pad;
+  double diag;    /* entry used for i == j */
+  double shift;   /* added to every diagonal entry */
+} hmat_kernel;
+
+/*
+ * Assembles the kernel matrix on the tree's points as an H-matrix: nearfield
+ * leaves dense, farfield leaves compressed on the device to relative Frobenius
+ * tolerance eps_in per block (same randomized compression as the product,
+ * applied to the kernel block evaluated on the fly).
+ * Errors: HMAT_ERR_ARG (unknown kind, eps_in not in (0,1), NULL), device errors,
+ * HMAT_ERR_NOT_CONVERGED with the result still returned.
+ */
+hmat_status hmat_assemble(hmat_tree t, const hmat_kernel* k, double eps_in, const hmat_opts* opts,
+                          hmat* out);
+
+/*
+ * Builds an H-matrix on tree t from host data: for every leaf block i (in the
+ * order of hmat_block_count/hmat_block_get) ranks[i] (farfield) and the leaf's
+ * data at pool + offsets[i]: farfield L (rows x rank) then R (cols x rank),
+ * nearfield the dense rows x cols block, all column-major.
+ */
+hmat_status hmat_from_blocks(hmat_tree t, const int32_t* ranks, const int64_t* offsets,
+                             const double* pool, hmat* out);
+
+hmat_status hmat_destroy(hmat M);
+
+/* ------------------------------------------------------------------------ */
+/* Product                                                                  */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * C = A B on the common block-cluster tree. For every farfield leaf the stored
+ * rank-k factors satisfy ||(AB)[t,s] - L R^T||_F <= ~eps ||(AB)[t,s]||_F with k
+ * close to the epsilon-rank; nearfield leaves are exact up to rounding.
+ *  A, B   unmodified; they must share one tree (HMAT_ERR_TREE_MISMATCH).
+ *  eps    in (0, 1), else HMAT_ERR_ARG.
+ *  opts   nullable (defaults).
+ *  C      receives a new H-matrix on the same tree.
+ * If farfield blocks exhaust max_growth, C is still returned, their best
+ * available factors are stored, stats->n_not_converged counts them and the
+ * call returns HMAT_ERR_NOT_CONVERGED.
+ */
+hmat_status hmat_multiply(hmat A, hmat B, double eps, const hmat_opts* opts, hmat* C);
+
+/*
+ * count independent products C[i] = A[i] B[i] (each pair on its own tree).
+ * status (host int32[count], nullable) receives the per-product status.
+ */
+hmat_status hmat_multiply_batched(const hmat* A, const hmat* B, int32_t count, double eps,
+                                  const hmat_opts* opts, hmat* C, int32_t* status);
+
+/* ------------------------------------------------------------------------ */
+/* Export                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Dense n x n copy of M into host memory out (column-major, leading dimension
+ * ld >= n); order 0 = original point order, 1 = cluster order.
+ */
+hmat_status hmat_to_dense(hmat M, double* out, int64_t ld, int32_t order);
+
+typedef struct {
+  int64_t row_begin, rows, col_begin, cols;  /* positions in cluster order */
+  int32_t level;
+  int32_t kind;   /* 1 = farfield (low rank), 2 = nearfield (dense) */
+  int32_t rank;   /* farfield rank, 0 for nearfield */
+  int32_t block;  /* id in hmat_tree_blocks order */
+} hmat_block_desc;
+
+/* Number of leaf blocks (farfield + nearfield), breadth-first leaf order. */
+hmat_status hmat_block_count(hmat M, int64_t* count);
+/*
+ * Leaf i: descriptor, and (if not NULL) its data in host memory: farfield
+ * U (rows x rank) and V (cols x rank) with block = U V^T; nearfield the dense
+ * rows x cols block in V_or_dense (U unused).
+ */
+hmat_status hmat_block_get(hmat M, int64_t i, hmat_block_desc* d, double* U, double* V_or_dense);
+/*
+ * Bulk export: ranks (host int32[count]), offsets (host int64[count], element
+ * offsets into the pool) and, if pool is not NULL, the pool itself (host
+ * float64[*pool_len]). Call first with pool = NULL to get *pool_len.
+ */
+hmat_status hmat_export(hmat M, int32_t* ranks, int64_t* offsets, double* pool, int64_t* pool_len);
+
+/* ------------------------------------------------------------------------ */
+/* Learned rank predictor (multi-layer perceptron 6-64-64-64-1, ReLU, fp32) */
+/* ------------------------------------------------------------------------ */
+
+enum { HMAT_N_FEATURES = 6 };
+
+typedef struct {
+  int32_t epochs;      /* passes over the data (default 200) */
+  int32_t batch;       /* minibatch size (default 256) */
+  float lr;            /* Adam step size (default 1e-3) */
+  float weight_decay;  /* default 0 */
+  uint64_t seed;       /* init and shuffling (default 1) */
+  void* stream;
+  float* loss_out;     /* host float[epochs], nullable: mean loss per epoch */
+} hmat_train_opts;
+
+void hmat_train_opts_default(hmat_train_opts* o);
+
+/* New model with seeded random weights (on the current device). */
+hmat_status hmat_rank_model_create(uint64_t seed, hmat_rank_model* out);
+hmat_status hmat_rank_model_destroy(hmat_rank_model m);
+/*
+ * Trains on m samples: feats host float[m * 6] row-major (level, log diam tau,
+ * log diam sigma, log dist, input-rank sum, term count; raw, the model
+ * standardises them), ranks host float[m]. Loss: mean squared error in the
+ * rank. Forward, backward and Adam run on the device.
+ */
+hmat_status hmat_rank_model_train(hmat_rank_model model, const float* feats, const float* ranks,
+                                  int64_t m, const hmat_train_opts* opts);
+/* Inference: pred host float[m]. */
+hmat_status hmat_rank_model_predict(hmat_rank_model model, const float* feats, int64_t m,
+                                    float* pred, void* stream);
+/* Parameters as host floats (count via *len when params is NULL). */
+hmat_status hmat_rank_model_get(hmat_rank_model model, float* params, int64_t* len);
+hmat_status hmat_rank_model_set(hmat_rank_model model, const float* params, int64_t len);
+/*
+ * One forward+backward of the loss on a batch without updating: grads host
+ * float[len] (same layout as hmat_rank_model_get), loss host float[1].
+ */
+hmat_status hmat_rank_model_grad(hmat_rank_model model, const float* feats, const float* ranks,
+                                 int64_t m, float* grads, float* loss);
+/*
+ * Features and ranks of the farfield blocks of the last product computed with
+ * a stats pointer into C (HMAT_RANK_ADAPTIVE): feats host float[n_far*6],
+ * ranks host float[n_far]; *count receives n_far (call with NULL outputs to
+ * query it).
+ */
+hmat_status hmat_product_features(hmat C, float* feats, float* ranks, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HMAT_H */

@@ -1,0 +1,377 @@
+// C ABI entry points: handles, error reporting, allocator hook, tree queries,
+// assembly, import/export. Every entry point catches everything and reports
+// through hmat_last_error().
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "hmat_internal.h"
+
+namespace hm {
+
+HMat* assemble_kernel(Tree* t, const hmat_kernel* k, double eps_in, const Opts& opts,
+                      int64_t* n_not_converged);
+hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** C);
+hmat_status multiply_batched(HMat* const* A, HMat* const* B, int32_t count, double eps, const Opts& opts,
+                             HMat** C, int32_t* status);
+
+static thread_local std::string g_err;
+void set_last_error(const std::string& msg) { g_err = msg; }
+
+static std::mutex g_alloc_mu;
+static void* (*g_alloc)(size_t, void*) = nullptr;
+static void (*g_free)(void*, void*) = nullptr;
+static void* g_ctx = nullptr;
+
+void* dev_alloc(size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 8;
+  if (g_alloc) {
+    p = g_alloc(bytes, g_ctx);
+    if (!p) throw Error(HMAT_ERR_OOM, "allocator hook failed for " + std::to_string(bytes) + " bytes");
+    return p;
+  }
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(HMAT_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+  }
+  return p;
+}
+
+void dev_free(void* p) {
+  if (!p) return;
+  if (g_free) {
+    g_free(p, g_ctx);
+    return;
+  }
+  (void)hipFree(p);
+}
+
+double now_seconds() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+Opts resolve_opts(const hmat_opts* o) {
+  Opts r;
+  hmat_opts_default(&r.o);
+  if (o) r.o = *o;
+  HM_REQUIRE(r.o.b0 >= 1 && r.o.b0 <= 32, HMAT_ERR_ARG, "b0 must be in [1, 32]");
+  HM_REQUIRE(r.o.growth >= 1 && r.o.growth <= 16, HMAT_ERR_ARG, "growth must be in [1, 16]");
+  HM_REQUIRE(r.o.probes >= 1 && r.o.probes <= 16, HMAT_ERR_ARG, "probes must be in [1, 16]");
+  HM_REQUIRE(r.o.max_growth >= 0 && r.o.max_growth <= 16, HMAT_ERR_ARG, "max_growth must be in [0, 16]");
+  HM_REQUIRE(r.o.p_l >= 0 && r.o.p_l <= 16, HMAT_ERR_ARG, "p_l must be in [0, 16]");
+  HM_REQUIRE(r.o.delta > 0.0 && r.o.delta <= 1.0, HMAT_ERR_ARG, "delta must be in (0, 1]");
+  HM_REQUIRE(r.o.precision >= 0 && r.o.precision <= 2, HMAT_ERR_ARG, "unknown precision");
+  HM_REQUIRE(r.o.rank_mode == HMAT_RANK_ADAPTIVE || r.o.rank_mode == HMAT_RANK_PREDICT, HMAT_ERR_ARG,
+             "unknown rank mode");
+  HM_REQUIRE(r.o.rank_mode != HMAT_RANK_PREDICT || r.o.rank_model != nullptr, HMAT_ERR_ARG,
+             "HMAT_RANK_PREDICT needs opts.rank_model");
+  return r;
+}
+
+HMat::~HMat() { tree_release(tree); }
+
+void HMat::upload_meta(hipStream_t s) {
+  d_rank.upload(rank, s);
+  d_off.upload(off, s);
+}
+
+void hmat_release(HMat* m) { delete m; }
+
+}  // namespace hm
+
+using namespace hm;
+
+#define API_BEGIN try {
+#define API_END                                   \
+  }                                               \
+  catch (const hm::Error& e) {                    \
+    set_last_error(e.what());                     \
+    return e.code;                                \
+  }                                               \
+  catch (const std::bad_alloc&) {                 \
+    set_last_error("host allocation failed");     \
+    return HMAT_ERR_OOM;                          \
+  }                                               \
+  catch (const std::exception& e) {               \
+    set_last_error(e.what());                     \
+    return HMAT_ERR_INTERNAL;                     \
+  }                                               \
+  catch (...) {                                   \
+    set_last_error("unknown error");              \
+    return HMAT_ERR_INTERNAL;                     \
+  }                                               \
+  set_last_error("");                             \
+  return HMAT_OK;
+
+extern "C" {
+
+const char* hmat_last_error(void) { return g_err.c_str(); }
+const char* hmat_version(void) { return "hmat-mi355x 0.1"; }
+
+hmat_status hmat_set_allocator(void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, void*), void* ctx) {
+  API_BEGIN
+  HM_REQUIRE((alloc_fn == nullptr) == (free_fn == nullptr), HMAT_ERR_ARG,
+             "alloc and free must be both set or both NULL");
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc = alloc_fn;
+  g_free = free_fn;
+  g_ctx = ctx;
+  API_END
+}
+
+void hmat_opts_default(hmat_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = HMAT_FP64;
+  o->rank_mode = HMAT_RANK_ADAPTIVE;
+  o->b0 = 8;
+  o->growth = 8;
+  o->probes = 8;
+  o->max_growth = 6;
+  o->p_l = 3;
+  o->delta = 0.05;
+  o->seed = 0x5eedull;
+}
+
+hmat_status hmat_build_tree(const double* xyz, int64_t n, int32_t leaf_size, double eta, int32_t split,
+                            hmat_tree* out) {
+  API_BEGIN
+  HM_REQUIRE(out != nullptr, HMAT_ERR_ARG, "out is NULL");
+  *out = reinterpret_cast<hmat_tree>(build_tree(xyz, n, leaf_size, eta, split));
+  API_END
+}
+
+hmat_status hmat_tree_destroy(hmat_tree t) {
+  API_BEGIN
+  tree_release(reinterpret_cast<Tree*>(t));
+  API_END
+}
+
+hmat_status hmat_tree_info(hmat_tree th, hmat_tree_info_t* out) {
+  API_BEGIN
+  HM_REQUIRE(th && out, HMAT_ERR_ARG, "NULL argument");
+  Tree* t = reinterpret_cast<Tree*>(th);
+  out->n = t->n;
+  out->leaf_size = t->leaf_size;
+  out->split = t->split;
+  out->eta = t->eta;
+  out->depth = t->depth;
+  out->n_clusters = int32_t(t->c_begin.size());
+  out->n_blocks = int64_t(t->b_tau.size());
+  int64_t nf = 0, nn = 0;
+  for (int32_t b : t->leaves) (t->b_kind[b] == KIND_F ? nf : nn)++;
+  out->n_far = nf;
+  out->n_near = nn;
+  out->csp = t->csp;
+  API_END
+}
+
+hmat_status hmat_tree_perm(hmat_tree th, int32_t* perm) {
+  API_BEGIN
+  HM_REQUIRE(th && perm, HMAT_ERR_ARG, "NULL argument");
+  Tree* t = reinterpret_cast<Tree*>(th);
+  std::memcpy(perm, t->perm.data(), sizeof(int32_t) * t->perm.size());
+  API_END
+}
+
+hmat_status hmat_tree_clusters(hmat_tree th, int32_t* begin, int32_t* size, int32_t* parent, int32_t* level) {
+  API_BEGIN
+  HM_REQUIRE(th, HMAT_ERR_ARG, "NULL tree");
+  Tree* t = reinterpret_cast<Tree*>(th);
+  size_t nc = t->c_begin.size();
+  if (begin) std::memcpy(begin, t->c_begin.data(), 4 * nc);
+  if (size) std::memcpy(size, t->c_size.data(), 4 * nc);
+  if (parent) std::memcpy(parent, t->c_parent.data(), 4 * nc);
+  if (level) std::memcpy(level, t->c_level.data(), 4 * nc);
+  API_END
+}
+
+hmat_status hmat_tree_blocks(hmat_tree th, int32_t* tau, int32_t* sigma, int32_t* level, int32_t* kind) {
+  API_BEGIN
+  HM_REQUIRE(th, HMAT_ERR_ARG, "NULL tree");
+  Tree* t = reinterpret_cast<Tree*>(th);
+  size_t nb = t->b_tau.size();
+  if (tau) std::memcpy(tau, t->b_tau.data(), 4 * nb);
+  if (sigma) std::memcpy(sigma, t->b_sigma.data(), 4 * nb);
+  if (level) std::memcpy(level, t->b_level.data(), 4 * nb);
+  if (kind) std::memcpy(kind, t->b_kind.data(), 4 * nb);
+  API_END
+}
+
+hmat_status hmat_assemble(hmat_tree th, const hmat_kernel* k, double eps_in, const hmat_opts* opts, hmat* out) {
+  API_BEGIN
+  HM_REQUIRE(th && k && out, HMAT_ERR_ARG, "NULL argument");
+  Opts o = resolve_opts(opts);
+  int64_t nc = 0;
+  HMat* M = assemble_kernel(reinterpret_cast<Tree*>(th), k, eps_in, o, &nc);
+  *out = reinterpret_cast<hmat>(M);
+  if (nc > 0) {
+    set_last_error(std::to_string(nc) + " farfield blocks did not reach eps_in");
+    return HMAT_ERR_NOT_CONVERGED;
+  }
+  API_END
+}
+
+hmat_status hmat_from_blocks(hmat_tree th, const int32_t* ranks, const int64_t* offsets, const double* pool,
+                             hmat* out) {
+  API_BEGIN
+  HM_REQUIRE(th && ranks && offsets && pool && out, HMAT_ERR_ARG, "NULL argument");
+  Tree* t = reinterpret_cast<Tree*>(th);
+  HMat* M = new HMat();
+  M->tree = t;
+  tree_retain(t);
+  const int64_t nb = int64_t(t->b_tau.size());
+  M->rank.assign(nb, 0);
+  M->off.assign(nb, -1);
+  int64_t total = 0;
+  std::vector<int64_t> len(t->leaves.size());
+  for (size_t i = 0; i < t->leaves.size(); ++i) {
+    int32_t b = t->leaves[i];
+    int64_t m = t->c_size[t->b_tau[b]], n = t->c_size[t->b_sigma[b]];
+    if (t->b_kind[b] == KIND_F) {
+      if (ranks[i] < 0 || ranks[i] > std::min(m, n)) {
+        delete M;
+        throw Error(HMAT_ERR_ARG, "rank out of range at leaf " + std::to_string(i));
+      }
+      M->rank[b] = ranks[i];
+      len[i] = int64_t(ranks[i]) * (m + n);
+    } else {
+      len[i] = m * n;
+    }
+    M->off[b] = total;
+    total += len[i];
+  }
+  std::vector<double> h(size_t(std::max<int64_t>(total, 1)));
+  for (size_t i = 0; i < t->leaves.size(); ++i)
+    std::memcpy(h.data() + M->off[t->leaves[i]], pool + offsets[i], 8 * len[i]);
+  M->pool_len = total;
+  hipStream_t s = 0;
+  M->pool.upload(h, s);
+  M->upload_meta(s);
+  HM_CHECK_HIP(hipStreamSynchronize(s));
+  *out = reinterpret_cast<hmat>(M);
+  API_END
+}
+
+hmat_status hmat_destroy(hmat m) {
+  API_BEGIN
+  hmat_release(reinterpret_cast<HMat*>(m));
+  API_END
+}
+
+hmat_status hmat_multiply(hmat A, hmat B, double eps, const hmat_opts* opts, hmat* C) {
+  API_BEGIN
+  HM_REQUIRE(A && B && C, HMAT_ERR_ARG, "NULL argument");
+  HM_REQUIRE(eps > 0.0 && eps < 1.0, HMAT_ERR_ARG, "eps must be in (0, 1)");
+  Opts o = resolve_opts(opts);
+  HMat* out = nullptr;
+  hmat_status st = multiply(reinterpret_cast<HMat*>(A), reinterpret_cast<HMat*>(B), eps, o, &out);
+  *C = reinterpret_cast<hmat>(out);
+  if (st != HMAT_OK) return st;
+  API_END
+}
+
+hmat_status hmat_multiply_batched(const hmat* A, const hmat* B, int32_t count, double eps, const hmat_opts* opts,
+                                  hmat* C, int32_t* status) {
+  API_BEGIN
+  HM_REQUIRE(A && B && C && count >= 0, HMAT_ERR_ARG, "bad argument");
+  HM_REQUIRE(eps > 0.0 && eps < 1.0, HMAT_ERR_ARG, "eps must be in (0, 1)");
+  Opts o = resolve_opts(opts);
+  hmat_status st = multiply_batched(reinterpret_cast<HMat* const*>(A), reinterpret_cast<HMat* const*>(B),
+                                    count, eps, o, reinterpret_cast<HMat**>(C), status);
+  if (st != HMAT_OK) return st;
+  API_END
+}
+
+static void fetch_pool(HMat* M, std::vector<double>& h) {
+  h.resize(size_t(std::max<int64_t>(M->pool_len, 1)));
+  HM_CHECK_HIP(hipMemcpy(h.data(), M->pool.p, 8 * size_t(M->pool_len), hipMemcpyDeviceToHost));
+}
+
+hmat_status hmat_to_dense(hmat mh, double* out, int64_t ld, int32_t order) {
+  API_BEGIN
+  HM_REQUIRE(mh && out, HMAT_ERR_ARG, "NULL argument");
+  HMat* M = reinterpret_cast<HMat*>(mh);
+  Tree* t = M->tree;
+  HM_REQUIRE(ld >= t->n, HMAT_ERR_ARG, "ld < n");
+  HM_REQUIRE(order == 0 || order == 1, HMAT_ERR_ARG, "order must be 0 or 1");
+  std::vector<double> h;
+  fetch_pool(M, h);
+  for (int32_t b : t->leaves) {
+    int64_t r0 = t->c_begin[t->b_tau[b]], m = t->c_size[t->b_tau[b]];
+    int64_t c0 = t->c_begin[t->b_sigma[b]], n = t->c_size[t->b_sigma[b]];
+    const double* d = h.data() + M->off[b];
+    for (int64_t j = 0; j < n; ++j)
+      for (int64_t i = 0; i < m; ++i) {
+        double v;
+        if (t->b_kind[b] == KIND_F) {
+          int k = M->rank[b];
+          v = 0.0;
+          for (int c = 0; c < k; ++c) v += d[c * m + i] * d[m * k + c * n + j];
+        } else {
+          v = d[j * m + i];
+        }
+        int64_t ri = order ? r0 + i : t->perm[r0 + i];
+        int64_t cj = order ? c0 + j : t->perm[c0 + j];
+        out[cj * ld + ri] = v;
+      }
+  }
+  API_END
+}
+
+hmat_status hmat_block_count(hmat mh, int64_t* count) {
+  API_BEGIN
+  HM_REQUIRE(mh && count, HMAT_ERR_ARG, "NULL argument");
+  *count = int64_t(reinterpret_cast<HMat*>(mh)->tree->leaves.size());
+  API_END
+}
+
+hmat_status hmat_block_get(hmat mh, int64_t i, hmat_block_desc* d, double* U, double* V) {
+  API_BEGIN
+  HM_REQUIRE(mh && d, HMAT_ERR_ARG, "NULL argument");
+  HMat* M = reinterpret_cast<HMat*>(mh);
+  Tree* t = M->tree;
+  HM_REQUIRE(i >= 0 && i < int64_t(t->leaves.size()), HMAT_ERR_ARG, "block index out of range");
+  int32_t b = t->leaves[i];
+  d->row_begin = t->c_begin[t->b_tau[b]];
+  d->rows = t->c_size[t->b_tau[b]];
+  d->col_begin = t->c_begin[t->b_sigma[b]];
+  d->cols = t->c_size[t->b_sigma[b]];
+  d->level = t->b_level[b];
+  d->kind = t->b_kind[b];
+  d->rank = t->b_kind[b] == KIND_F ? M->rank[b] : 0;
+  d->block = b;
+  if (t->b_kind[b] == KIND_F) {
+    int64_t k = M->rank[b];
+    if (U && k) HM_CHECK_HIP(hipMemcpy(U, M->pool.p + M->off[b], 8 * k * d->rows, hipMemcpyDeviceToHost));
+    if (V && k)
+      HM_CHECK_HIP(hipMemcpy(V, M->pool.p + M->off[b] + k * d->rows, 8 * k * d->cols, hipMemcpyDeviceToHost));
+  } else if (V) {
+    HM_CHECK_HIP(hipMemcpy(V, M->pool.p + M->off[b], 8 * d->rows * d->cols, hipMemcpyDeviceToHost));
+  }
+  API_END
+}
+
+hmat_status hmat_export(hmat mh, int32_t* ranks, int64_t* offsets, double* pool, int64_t* pool_len) {
+  API_BEGIN
+  HM_REQUIRE(mh && pool_len, HMAT_ERR_ARG, "NULL argument");
+  HMat* M = reinterpret_cast<HMat*>(mh);
+  Tree* t = M->tree;
+  for (size_t i = 0; i < t->leaves.size(); ++i) {
+    int32_t b = t->leaves[i];
+    if (ranks) ranks[i] = M->rank[b];
+    if (offsets) offsets[i] = M->off[b];
+  }
+  if (pool) {
+    HM_REQUIRE(*pool_len >= M->pool_len, HMAT_ERR_ARG, "pool buffer too small");
+    if (M->pool_len)
+      HM_CHECK_HIP(hipMemcpy(pool, M->pool.p, 8 * size_t(M->pool_len), hipMemcpyDeviceToHost));
+  }
+  *pool_len = M->pool_len;
+  API_END
+}
+
+}  // extern "C"

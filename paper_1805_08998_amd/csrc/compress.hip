@@ -1,0 +1,297 @@
+// Per-target kernels of the randomized compression (orthogonalisation, probe
+// residual, residual check, core SVD and truncation, factor output). One
+// workgroup of 256 threads per target; panels stay in global memory (they are
+// small enough to live in L2 while a workgroup works on them).
+#include "compress.h"
+#include "device_common.h"
+
+namespace hm {
+
+constexpr int NT = 256;
+
+// ---------------------------------------------------------------- Gaussian matrix
+__global__ void k_fill_gaussian(double* __restrict__ om, int64_t n, int32_t ncol, uint32_t k0,
+                                uint32_t k1) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int32_t j = blockIdx.y;
+  if (i >= n || j >= ncol) return;
+  U4 c{uint32_t(i), uint32_t(j), uint32_t(i >> 32), 0x0A11CE5u};
+  om[int64_t(j) * n + i] = gaussian_from(philox4x32_10(c, k0, k1));
+}
+
+void launch_fill_gaussian(double* omega, int64_t n, int32_t ncol, uint64_t seed, hipStream_t s) {
+  if (n <= 0 || ncol <= 0) return;
+  dim3 grid(unsigned((n + 255) / 256), unsigned(ncol));
+  hipLaunchKernelGGL(k_fill_gaussian, grid, dim3(256), 0, s, omega, n, ncol, uint32_t(seed),
+                     uint32_t(seed >> 32));
+  HM_CHECK_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- helpers
+// h[j] = Q[:, j] . v for j < r (Q ld m), computed wave-per-column.
+__device__ void dots_against(const double* Q, int m, int r, const double* v, double* h) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int j = w; j < r; j += NT / 64) {
+    const double* q = Q + int64_t(j) * m;
+    double acc = 0.0;
+    for (int i = lane; i < m; i += 64) acc += q[i] * v[i];
+    acc = wave_sum(acc);
+    if (lane == 0) h[j] = acc;
+  }
+  __syncthreads();
+}
+
+// v -= Q[:, :r] h
+__device__ void sub_combination(const double* Q, int m, int r, const double* h, double* v) {
+  for (int i = threadIdx.x; i < m; i += NT) {
+    double acc = v[i];
+    for (int j = 0; j < r; ++j) acc -= Q[int64_t(j) * m + i] * h[j];
+    v[i] = acc;
+  }
+  __syncthreads();
+}
+
+__device__ double norm2_col(const double* v, int m, double* red) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < m; i += NT) acc += v[i] * v[i];
+  return block_sum<NT>(acc, red);
+}
+
+// ---------------------------------------------------------------- orthogonalisation
+__global__ void __launch_bounds__(NT) k_orth_append(CTarget* __restrict__ tg, int nt, int src, int cnt,
+                                                    int cap) {
+  __shared__ double h[128];
+  __shared__ double red[NT / 64];
+  CTarget& T = tg[blockIdx.x];
+  if (!T.active) return;
+  const int m = T.m;
+  double* Y = T.Y;
+  int r = T.r;
+  for (int c = src; c < src + cnt; ++c) {
+    double* v = Y + int64_t(c) * m;
+    double n0 = norm2_col(v, m, red);
+    for (int pass = 0; pass < 2; ++pass) {
+      dots_against(Y, m, r, v, h);
+      sub_combination(Y, m, r, h, v);
+    }
+    double n1 = norm2_col(v, m, red);
+    bool keep = (r < cap) && n1 > 0.0 && n1 > 1e-26 * n0;  // relative residual > 1e-13
+    if (keep) {
+      double inv = 1.0 / sqrt(n1);
+      double* dst = Y + int64_t(r) * m;
+      for (int i = threadIdx.x; i < m; i += NT) dst[i] = v[i] * inv;
+      __syncthreads();
+      ++r;
+    }
+  }
+  if (threadIdx.x == 0) T.r = r;
+}
+
+void launch_orth_append(CTarget* t, int nt, int src, int cnt, const CParams& p, hipStream_t s) {
+  if (nt <= 0) return;
+  hipLaunchKernelGGL(k_orth_append, dim3(nt), dim3(NT), 0, s, t, nt, src, cnt, p.cap);
+  HM_CHECK_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- probe residual
+__global__ void __launch_bounds__(NT) k_probe_residual(CTarget* __restrict__ tg, int nt, int cap, int g) {
+  __shared__ double h[128];
+  __shared__ double red[NT / 64];
+  CTarget& T = tg[blockIdx.x];
+  if (!T.active) return;
+  const int m = T.m, r = T.r;
+  double* Y = T.Y;
+  double e2 = 0.0;
+  for (int c = cap; c < cap + g; ++c) {
+    double* v = Y + int64_t(c) * m;
+    for (int pass = 0; pass < 2; ++pass) {
+      dots_against(Y, m, r, v, h);
+      sub_combination(Y, m, r, h, v);
+    }
+    e2 += norm2_col(v, m, red);
+  }
+  if (threadIdx.x == 0) T.E2 = e2 / double(g);
+}
+
+void launch_probe_residual(CTarget* t, int nt, const CParams& p, hipStream_t s) {
+  if (nt <= 0) return;
+  hipLaunchKernelGGL(k_probe_residual, dim3(nt), dim3(NT), 0, s, t, nt, p.cap, p.g);
+  HM_CHECK_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- residual check
+__global__ void __launch_bounds__(NT) k_check(CTarget* __restrict__ tg, int nt, int cap, int g, double eps,
+                                              double delta, int32_t* __restrict__ pending) {
+  __shared__ double red[NT / 64];
+  CTarget& T = tg[blockIdx.x];
+  if (!T.active) {
+    if (threadIdx.x == 0) pending[blockIdx.x] = 0;
+    return;
+  }
+  const int64_t len = int64_t(T.n) * T.rz;
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < len; i += NT) acc += T.Z[i] * T.Z[i];
+  acc = block_sum<NT>(acc, red);
+  if (threadIdx.x == 0) {
+    T.nB2 = acc;
+    double lim = delta * eps;
+    bool ok = T.E2 <= lim * lim * (acc + T.E2);
+    // a zero sketch of a zero operator passes (E2 = 0)
+    T.done = ok ? 1 : 0;
+    int more = (!ok && T.r + g <= cap) ? 1 : 0;
+    pending[blockIdx.x] = more;
+  }
+}
+
+void launch_check(CTarget* t, int nt, const CParams& p, int32_t* pending, hipStream_t s) {
+  if (nt <= 0) return;
+  hipLaunchKernelGGL(k_check, dim3(nt), dim3(NT), 0, s, t, nt, p.cap, p.g, p.eps, p.delta, pending);
+  HM_CHECK_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- core SVD + truncation
+constexpr int CAPMAX = 64;
+
+__global__ void __launch_bounds__(NT) k_core(CTarget* __restrict__ tg, int nt, int cap, double eps) {
+  __shared__ double h[CAPMAX];
+  __shared__ double red[NT / 64];
+  __shared__ double M[CAPMAX * CAPMAX];  // Rz^T, column-major, ld CAPMAX
+  __shared__ double J[CAPMAX * CAPMAX];
+  __shared__ double sig[CAPMAX];
+  __shared__ int order[CAPMAX];
+  CTarget& T = tg[blockIdx.x];
+  const int n = T.n, r = T.rz;
+  double* Z = T.Z;
+  for (int i = threadIdx.x; i < CAPMAX * CAPMAX; i += NT) {
+    M[i] = 0.0;
+    J[i] = 0.0;
+  }
+  __syncthreads();
+  // CGS2 QR of Z (n x r) in place; R(i, j) goes to M(j, i)
+  for (int j = 0; j < r; ++j) {
+    double* v = Z + int64_t(j) * n;
+    double n0 = norm2_col(v, n, red);
+    for (int pass = 0; pass < 2; ++pass) {
+      dots_against(Z, n, j, v, h);
+      if (threadIdx.x < j) M[threadIdx.x * CAPMAX + j] += h[threadIdx.x];  // M(j, i) = R(i, j)
+      __syncthreads();
+      sub_combination(Z, n, j, h, v);
+    }
+    double n1 = norm2_col(v, n, red);
+    bool keep = n1 > 0.0 && n1 > 1e-28 * n0;
+    double d = keep ? sqrt(n1) : 0.0;
+    double inv = keep ? 1.0 / d : 0.0;
+    for (int i = threadIdx.x; i < n; i += NT) v[i] *= inv;
+    if (threadIdx.x == 0) M[j * CAPMAX + j] = d;
+    __syncthreads();
+  }
+  // one-sided Jacobi on the columns of M (r x r), accumulating J; wave 0 only
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    for (int i = 0; i < r; ++i)
+      if (lane < r) J[i * CAPMAX + lane] = (lane == i) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+      int rotated = 0;
+      for (int p = 0; p < r - 1; ++p)
+        for (int q = p + 1; q < r; ++q) {
+          double mp = lane < r ? M[p * CAPMAX + lane] : 0.0;
+          double mq = lane < r ? M[q * CAPMAX + lane] : 0.0;
+          double a = wave_sum(mp * mp), b = wave_sum(mq * mq), c = wave_sum(mp * mq);
+          if (fabs(c) <= 1e-15 * sqrt(a * b) || c == 0.0) continue;
+          rotated = 1;
+          double zeta = (b - a) / (2.0 * c);
+          double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+          if (lane < r) {
+            M[p * CAPMAX + lane] = cs * mp - sn * mq;
+            M[q * CAPMAX + lane] = sn * mp + cs * mq;
+            double jp = J[p * CAPMAX + lane], jq = J[q * CAPMAX + lane];
+            J[p * CAPMAX + lane] = cs * jp - sn * jq;
+            J[q * CAPMAX + lane] = sn * jp + cs * jq;
+          }
+        }
+      if (!rotated) break;
+    }
+    for (int j = 0; j < r; ++j) {
+      double mj = lane < r ? M[j * CAPMAX + lane] : 0.0;
+      double s2 = wave_sum(mj * mj);
+      if (lane == 0) sig[j] = sqrt(s2);
+    }
+    if (lane == 0) {
+      for (int j = 0; j < r; ++j) order[j] = j;
+      for (int a = 1; a < r; ++a) {  // insertion sort, descending
+        int x = order[a];
+        int b = a - 1;
+        while (b >= 0 && sig[order[b]] < sig[x]) {
+          order[b + 1] = order[b];
+          --b;
+        }
+        order[b + 1] = x;
+      }
+      double total = 0.0;
+      for (int j = 0; j < r; ++j) total += sig[j] * sig[j];
+      double thr = eps * eps * (total + T.E2) - T.E2;
+      int k = r;
+      double tail = 0.0;  // tail(k) = sum_{i >= k} sigma_i^2 in sorted order
+      for (int kk = r; kk >= 0; --kk) {
+        if (kk < r) tail += sig[order[kk]] * sig[order[kk]];
+        if (tail <= thr) k = kk;
+        else break;
+      }
+      T.k = k;
+      T.nB2 = total;
+    }
+  }
+  __syncthreads();
+  // store the sorted W (= M) and J columns plus sigma in core
+  double* core = T.core;
+  for (int idx = threadIdx.x; idx < r * r; idx += NT) {
+    int j = idx / r, i = idx % r;
+    int src = order[j];
+    core[idx] = M[src * CAPMAX + i];
+    core[cap * cap + idx] = J[src * CAPMAX + i];
+  }
+  for (int j = threadIdx.x; j < r; j += NT) core[2 * cap * cap + j] = sig[order[j]];
+}
+
+void launch_core(CTarget* t, int nt, const CParams& p, hipStream_t s) {
+  if (nt <= 0) return;
+  if (p.cap > CAPMAX) throw Error(HMAT_ERR_INTERNAL, "column capacity above 64");
+  hipLaunchKernelGGL(k_core, dim3(nt), dim3(NT), 0, s, t, nt, p.cap, p.eps);
+  HM_CHECK_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- factor output
+__global__ void __launch_bounds__(NT) k_write_factors(const CTarget* __restrict__ tg, int nt, int cap,
+                                                      double* __restrict__ pool) {
+  const CTarget& T = tg[blockIdx.x];
+  const int m = T.m, n = T.n, r = T.rz, k = T.k;
+  if (k == 0) return;
+  const double* W = T.core;
+  const double* J = T.core + cap * cap;
+  double* L = pool + T.out_off;
+  double* R = L + int64_t(m) * k;
+  // rows of both outputs are independent: one thread per row, k columns
+  for (int i = threadIdx.x; i < m; i += NT) {
+    for (int c = 0; c < k; ++c) {
+      double acc = 0.0;
+      for (int j = 0; j < r; ++j) acc += T.Y[int64_t(j) * m + i] * W[c * r + j];
+      L[int64_t(c) * m + i] = acc;
+    }
+  }
+  for (int i = threadIdx.x; i < n; i += NT) {
+    for (int c = 0; c < k; ++c) {
+      double acc = 0.0;
+      for (int j = 0; j < r; ++j) acc += T.Z[int64_t(j) * n + i] * J[c * r + j];
+      R[int64_t(c) * n + i] = acc;
+    }
+  }
+}
+
+void launch_write_factors(CTarget* t, int nt, const CParams& p, double* pool, hipStream_t s) {
+  if (nt <= 0) return;
+  hipLaunchKernelGGL(k_write_factors, dim3(nt), dim3(NT), 0, s, t, nt, p.cap, pool);
+  HM_CHECK_HIP(hipGetLastError());
+}
+
+}  // namespace hm
