@@ -67,7 +67,9 @@ __global__ void __launch_bounds__(NT) k_orth_append(CTarget* __restrict__ tg, in
   const int m = T.m;
   double* Y = T.Y;
   int r = T.r;
-  for (int c = src; c < src + cnt; ++c) {
+  // the first sketch block has a per-target width (w0 <= cnt)
+  const int cnt_t = (src == 0 && T.w0 > 0 && T.w0 < cnt) ? T.w0 : cnt;
+  for (int c = src; c < src + cnt_t; ++c) {
     double* v = Y + int64_t(c) * m;
     double n0 = norm2_col(v, m, red);
     for (int pass = 0; pass < 2; ++pass) {

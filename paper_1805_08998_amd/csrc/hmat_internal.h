@@ -65,7 +65,10 @@ struct DevBuf {
   }
   void upload(const T* h, size_t count, hipStream_t s) {
     if (count > n) alloc(count);
-    if (count) HM_CHECK_HIP(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, s));
+    if (count) {
+      HM_CHECK_HIP(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, s));
+      HM_CHECK_HIP(hipStreamSynchronize(s));  // the host buffer may change right after
+    }
   }
   void upload(const std::vector<T>& v, hipStream_t s) { upload(v.data(), v.size(), s); }
 };

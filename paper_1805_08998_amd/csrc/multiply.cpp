@@ -1,0 +1,936 @@
+// Host driver of the product C = A B (Algorithms 3 and 4 of the paper, breadth
+// first, with the blocked randomized compression of Section 4).
+//
+// 1. Symbolic restriction over the whole block tree (Algorithm 3): for every
+//    block the low-rank terms created at it and its list of pairs
+//    (A[tau, rho], B[rho, sigma]). Terms of ancestors are inherited by index
+//    shift and never copied.
+// 2. Creation of the low-rank terms in subtree batches (memory bound):
+//    FF: core R_A^T L_B; FH: B[rho', sigma']^T R_A; HF: A[tau', rho'] L_B; a pair
+//    whose middle cluster is a leaf keeps both dense factors as a term.
+// 3. Targets in chunks: farfield leaves are compressed (sketch + probe, CGS2,
+//    projection, growth, core SVD, truncation); nearfield leaves are evaluated
+//    by applying their sum-expression to the identity.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "compress.h"
+#include "product_kernels.h"
+
+namespace hm {
+
+void launch_leaf_p1(const LeafItem* items, size_t n, const Task* tasks, const TDesc* td, const TreeView& tv,
+                    const MatView& ma, const MatView& mb, double* ws, hipStream_t s);
+void launch_subtree_p2(const RowItem* items, size_t n, const Task* tasks, const TDesc* td, const TreeView& tv,
+                       const MatView& ma, const MatView& mb, const double* ws, hipStream_t s);
+void launch_term_p1(const TermItem* items, size_t n, const TDesc* td, const TInfo* ti, const TreeView& tv,
+                    double* vbuf, hipStream_t s);
+void launch_gather(const RowItem* items, size_t n, const TDesc* td, const TInfo* ti, const HPair* hp,
+                   const TreeView& tv, const double* vbuf, hipStream_t s);
+
+namespace {
+
+enum { T_FF = 0, T_FH = 1, T_HF = 2, T_GAP = 3 };
+
+struct SymTerm {
+  int32_t type;
+  int32_t child;  // block the term belongs to
+  int32_t a_blk, b_blk;
+  int32_t kl, kr;
+  int32_t batch;
+  int64_t data_off;  // offset of created data in the batch's pool (-1 none)
+};
+
+// Depth-first order of the leaves, the leaf range of every block, and per matrix
+// prefix sums of farfield ranks over that order.
+struct DfsInfo {
+  std::vector<int32_t> dfs_of_block;  // leaf block -> dfs index (else -1)
+  std::vector<int32_t> lo, hi;        // per block
+  std::vector<int32_t> dfs_block;     // dfs index -> block
+};
+
+DfsInfo dfs_order(const Tree& t) {
+  const int64_t nb = int64_t(t.b_tau.size());
+  DfsInfo d;
+  d.dfs_of_block.assign(nb, -1);
+  d.lo.assign(nb, 0);
+  d.hi.assign(nb, 0);
+  std::vector<std::pair<int32_t, int>> st;  // (block, state)
+  st.push_back({0, 0});
+  while (!st.empty()) {
+    auto [b, s] = st.back();
+    st.pop_back();
+    if (s == 0) {
+      d.lo[b] = int32_t(d.dfs_block.size());
+      if (t.b_nchild[b] == 0) {
+        d.dfs_of_block[b] = int32_t(d.dfs_block.size());
+        d.dfs_block.push_back(b);
+        d.hi[b] = int32_t(d.dfs_block.size());
+      } else {
+        st.push_back({b, 1});
+        for (int i = t.b_nchild[b] - 1; i >= 0; --i) st.push_back({t.b_child0[b] + i, 0});
+      }
+    } else {
+      d.hi[b] = int32_t(d.dfs_block.size());
+    }
+  }
+  return d;
+}
+
+struct DevMat {
+  DevBuf<int64_t> kpref;
+  std::vector<int64_t> hkpref;
+  MatView view(const HMat* M) const { return MatView{M->pool.p, M->d_rank.p, M->d_off.p, kpref.p}; }
+};
+
+void build_kpref(const HMat* M, const DfsInfo& d, DevMat& dm, hipStream_t s) {
+  dm.hkpref.assign(d.dfs_block.size() + 1, 0);
+  const Tree& t = *M->tree;
+  for (size_t i = 0; i < d.dfs_block.size(); ++i) {
+    int32_t b = d.dfs_block[i];
+    dm.hkpref[i + 1] = dm.hkpref[i] + (t.b_kind[b] == KIND_F ? M->rank[b] : 0);
+  }
+  dm.kpref.upload(dm.hkpref, s);
+}
+
+struct Ctx {
+  const Tree* t;
+  const HMat* A;
+  const HMat* B;
+  hipStream_t s;
+  DfsInfo dfs;
+  DevMat da, db;
+  MatView ma, mb;
+  TreeView tv;
+  DevBuf<int32_t> b_parent, b_dfs, group_ptr;
+  DevBuf<Term> terms;
+  std::vector<SymTerm> sym;
+  std::vector<int32_t> group_ptr_h;
+  std::vector<int32_t> hptr, hrho;  // pairs per block
+  std::vector<Term> hterms;
+  hmat_stats st{};
+  double eps;
+  Opts opts;
+
+  int32_t m_of(int32_t b) const { return t->c_size[t->b_tau[b]]; }
+  int32_t n_of(int32_t b) const { return t->c_size[t->b_sigma[b]]; }
+  int32_t rank_a(int32_t b) const { return A->rank[b]; }
+  int32_t rank_b(int32_t b) const { return B->rank[b]; }
+};
+
+// ------------------------------------------------------------------ symbolic restriction
+void symbolic(Ctx& c) {
+  const Tree& t = *c.t;
+  const int64_t nb = int64_t(t.b_tau.size());
+  c.group_ptr_h.assign(nb + 1, 0);
+  c.hptr.assign(nb + 1, 0);
+  std::vector<std::vector<int32_t>> H(nb);  // built per level, released as we go
+  H[0].push_back(0);
+  std::vector<int32_t> gcount(nb, 0), hcount(nb, 0);
+  // pass over blocks in breadth-first order: children of b get their lists now
+  std::vector<std::vector<SymTerm>> per_block_terms(nb);
+  for (int64_t b = 0; b < nb; ++b) {
+    if (t.b_kind[b] == KIND_INNER) {
+      for (int ci = 0; ci < t.b_nchild[b]; ++ci) {
+        const int32_t ch = t.b_child0[b] + ci;
+        const int32_t tau2 = t.b_tau[ch], sig2 = t.b_sigma[ch];
+        auto& terms = per_block_terms[ch];
+        auto& hl = H[ch];
+        for (int32_t rho : H[b]) {
+          if (t.c_nchild[rho] == 0) {
+            // middle cluster is a leaf: both factors are nearfield leaves of the parent level
+            int32_t a_blk = t.find_block(t.b_tau[b], rho);
+            int32_t b_blk = t.find_block(rho, t.b_sigma[b]);
+            if (a_blk < 0 || b_blk < 0) throw Error(HMAT_ERR_INTERNAL, "missing leaf pair");
+            SymTerm s{T_GAP, ch, a_blk, b_blk, t.c_size[rho], t.c_size[rho], 0, -1};
+            terms.push_back(s);
+            continue;
+          }
+          for (int i = 0; i < t.c_nchild[rho]; ++i) {
+            const int32_t r2 = t.c_child0[rho] + i;
+            const int32_t b1 = t.find_block(tau2, r2);
+            const int32_t b2 = t.find_block(r2, sig2);
+            if (b1 < 0 || b2 < 0) throw Error(HMAT_ERR_INTERNAL, "missing son block in restriction");
+            const bool f1 = t.b_kind[b1] == KIND_F, f2 = t.b_kind[b2] == KIND_F;
+            if (f1 && f2) {
+              if (c.rank_a(b1) && c.rank_b(b2))
+                terms.push_back(SymTerm{T_FF, ch, b1, b2, c.rank_a(b1), c.rank_b(b2), 0, -1});
+            } else if (f1) {
+              if (c.rank_a(b1)) terms.push_back(SymTerm{T_FH, ch, b1, b2, c.rank_a(b1), c.rank_a(b1), 0, -1});
+            } else if (f2) {
+              if (c.rank_b(b2)) terms.push_back(SymTerm{T_HF, ch, b1, b2, c.rank_b(b2), c.rank_b(b2), 0, -1});
+            } else {
+              hl.push_back(r2);
+            }
+          }
+        }
+      }
+      if (b > 0) {
+        std::vector<int32_t>().swap(H[b]);  // parent's list no longer needed except for targets
+      }
+    }
+  }
+  // H lists of leaves are needed by the targets; inner lists were released. Rebuild the
+  // CSR from what remains (leaves keep theirs).
+  for (int64_t b = 0; b < nb; ++b) {
+    c.group_ptr_h[b + 1] = c.group_ptr_h[b] + int32_t(per_block_terms[b].size());
+    c.hptr[b + 1] = c.hptr[b] + int32_t(t.b_kind[b] == KIND_INNER ? 0 : H[b].size());
+  }
+  c.sym.reserve(c.group_ptr_h[nb]);
+  for (int64_t b = 0; b < nb; ++b)
+    for (auto& s : per_block_terms[b]) c.sym.push_back(s);
+  c.hrho.reserve(c.hptr[nb]);
+  for (int64_t b = 0; b < nb; ++b)
+    if (t.b_kind[b] != KIND_INNER)
+      for (int32_t r : H[b]) c.hrho.push_back(r);
+}
+
+// ------------------------------------------------------------------ creation of terms
+struct Creation {
+  std::vector<Task> tasks;
+  std::vector<LeafItem> leaf_items;
+  std::vector<RowItem> row_items;
+  int64_t ws_len = 0;
+};
+
+void add_subtree_rows(const Tree& t, int32_t owner, int32_t cluster, std::vector<RowItem>& rows) {
+  for (int32_t lc = t.c_lc_begin[cluster]; lc < t.c_lc_end[cluster]; ++lc) {
+    int32_t cl = t.leaf_clusters[lc];
+    for (int ch = 0; ch * 64 < t.c_size[cl]; ++ch) rows.push_back(RowItem{owner, lc, ch, 0});
+  }
+}
+
+// leaf items of a subtree task; returns the workspace (doubles) its leaf products need
+int64_t add_subtree_leaves(const Ctx& c, int32_t owner, int mat, int32_t q, std::vector<LeafItem>& items) {
+  const Tree& t = *c.t;
+  const HMat* M = mat ? c.B : c.A;
+  const DevMat& dm = mat ? c.db : c.da;
+  for (int32_t i = c.dfs.lo[q]; i < c.dfs.hi[q]; ++i) {
+    int32_t b = c.dfs.dfs_block[i];
+    if (t.b_kind[b] == KIND_F && M->rank[b] > 0) items.push_back(LeafItem{owner, b});
+  }
+  return (dm.hkpref[c.dfs.hi[q]] - dm.hkpref[c.dfs.lo[q]]) * PW;
+}
+
+void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& pool_out) {
+  const Tree& t = *c.t;
+  hipStream_t s = c.s;
+  // data layout in the pool
+  int64_t pos = 0;
+  for (int32_t i : which) {
+    SymTerm& st = c.sym[i];
+    if (st.type == T_FF) st.data_off = pos, pos += int64_t(st.kl) * st.kr;
+    else if (st.type == T_FH) st.data_off = pos, pos += int64_t(st.kl) * c.n_of(st.child);
+    else if (st.type == T_HF) st.data_off = pos, pos += int64_t(st.kl) * c.m_of(st.child);
+    else st.data_off = -1;
+  }
+  pool_out.alloc(size_t(std::max<int64_t>(pos, 1)));
+  double* P = pool_out.p;
+  // FF cores: leaf products only, written straight into the pool
+  Creation ff, fh;
+  for (int32_t i : which) {
+    const SymTerm& st = c.sym[i];
+    if (st.type == T_FF) {
+      const int32_t rho = t.b_sigma[st.a_blk];
+      const double* LB = c.B->pool.p + c.B->off[st.b_blk];
+      for (int j0 = 0; j0 < st.kr; j0 += PW) {
+        Task tk{};
+        tk.X = LB + int64_t(j0) * t.c_size[rho];
+        tk.ldx = t.c_size[rho];
+        tk.mat = 0;
+        tk.q = st.a_blk;
+        tk.trans = 0;
+        tk.t = -1;
+        tk.w = std::min(PW, st.kr - j0);
+        tk.lo = c.dfs.lo[st.a_blk];
+        tk.tws = st.data_off + int64_t(j0) * st.kl;
+        ff.leaf_items.push_back(LeafItem{int32_t(ff.tasks.size()), st.a_blk});
+        ff.tasks.push_back(tk);
+      }
+    } else if (st.type == T_FH || st.type == T_HF) {
+      const bool isfh = st.type == T_FH;
+      const int32_t rho = isfh ? t.b_tau[st.b_blk] : t.b_sigma[st.a_blk];
+      const int32_t nrho = t.c_size[rho];
+      const double* X;
+      if (isfh) X = c.A->pool.p + c.A->off[st.a_blk] + int64_t(st.kl) * c.m_of(st.a_blk);  // R_A
+      else X = c.B->pool.p + c.B->off[st.b_blk];                                            // L_B
+      const int32_t outn = isfh ? c.n_of(st.child) : c.m_of(st.child);
+      for (int j0 = 0; j0 < st.kl; j0 += PW) {
+        Task tk{};
+        tk.X = X + int64_t(j0) * nrho;
+        tk.ldx = nrho;
+        tk.Y = P + st.data_off + int64_t(j0) * outn;
+        tk.ldy = outn;
+        tk.mat = isfh ? 1 : 0;
+        tk.q = isfh ? st.b_blk : st.a_blk;
+        tk.trans = isfh ? 1 : 0;
+        tk.t = -1;
+        tk.w = std::min(PW, st.kl - j0);
+        tk.lo = c.dfs.lo[tk.q];
+        tk.tws = fh.ws_len;
+        const int32_t owner = int32_t(fh.tasks.size());
+        fh.ws_len += add_subtree_leaves(c, owner, tk.mat, tk.q, fh.leaf_items);
+        add_subtree_rows(t, owner, isfh ? t.b_sigma[tk.q] : t.b_tau[tk.q], fh.row_items);
+        fh.tasks.push_back(tk);
+      }
+    }
+  }
+  if (!ff.tasks.empty()) {
+    DevBuf<Task> dt;
+    dt.upload(ff.tasks, s);
+    DevBuf<LeafItem> dl;
+    dl.upload(ff.leaf_items, s);
+    launch_leaf_p1(dl.p, ff.leaf_items.size(), dt.p, nullptr, c.tv, c.ma, c.mb, P, s);
+    HM_CHECK_HIP(hipStreamSynchronize(s));
+  }
+  if (!fh.tasks.empty()) {
+    DevBuf<Task> dt;
+    dt.upload(fh.tasks, s);
+    DevBuf<LeafItem> dl;
+    dl.upload(fh.leaf_items, s);
+    DevBuf<RowItem> dr;
+    dr.upload(fh.row_items, s);
+    DevBuf<double> ws(size_t(std::max<int64_t>(fh.ws_len, 1)));
+    launch_leaf_p1(dl.p, fh.leaf_items.size(), dt.p, nullptr, c.tv, c.ma, c.mb, ws.p, s);
+    launch_subtree_p2(dr.p, fh.row_items.size(), dt.p, nullptr, c.tv, c.ma, c.mb, ws.p, s);
+    HM_CHECK_HIP(hipStreamSynchronize(s));
+  }
+  // device descriptors of these terms
+  for (int32_t i : which) {
+    const SymTerm& st = c.sym[i];
+    Term& T = c.hterms[i];
+    const double* pa = c.A->pool.p + c.A->off[st.a_blk];
+    const double* pb = c.B->pool.p + c.B->off[st.b_blk];
+    const int32_t tau2 = t.b_tau[st.child], sig2 = t.b_sigma[st.child];
+    T.kl = st.kl;
+    T.kr = st.kr;
+    T.rtrans = 0;
+    T.core = nullptr;
+    switch (st.type) {
+      case T_FF: {
+        const int32_t m = c.m_of(st.a_blk), nrho = c.n_of(st.a_blk), nsig = c.n_of(st.b_blk);
+        (void)nrho;
+        T.L = pa;  // L_A (tau' x kA)
+        T.ldl = m;
+        T.lrow0 = t.c_begin[tau2];
+        T.R = pb + int64_t(st.kr) * c.m_of(st.b_blk);  // R_B (sigma' x kB)
+        T.ldr = nsig;
+        T.rrow0 = t.c_begin[sig2];
+        T.core = P + st.data_off;
+        break;
+      }
+      case T_FH:
+        T.L = pa;
+        T.ldl = c.m_of(st.a_blk);
+        T.lrow0 = t.c_begin[tau2];
+        T.R = P + st.data_off;
+        T.ldr = c.n_of(st.child);
+        T.rrow0 = t.c_begin[sig2];
+        break;
+      case T_HF:
+        T.L = P + st.data_off;
+        T.ldl = c.m_of(st.child);
+        T.lrow0 = t.c_begin[tau2];
+        T.R = pb + int64_t(st.kr) * c.m_of(st.b_blk);
+        T.ldr = c.n_of(st.b_blk);
+        T.rrow0 = t.c_begin[sig2];
+        break;
+      default: {  // both factors dense leaves of the parent level: A[tau, rho] and B[rho, sigma]
+        T.L = pa;
+        T.ldl = c.m_of(st.a_blk);
+        T.lrow0 = t.c_begin[t.b_tau[st.a_blk]];
+        T.R = pb;  // stored rho x sigma, read as R(j, c) = B[c + j * #rho]
+        T.ldr = c.m_of(st.b_blk);
+        T.rrow0 = t.c_begin[t.b_sigma[st.b_blk]];
+        T.rtrans = 1;
+        break;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ target chunks
+struct Chunk {
+  std::vector<int32_t> blocks;  // target blocks
+  std::vector<TInfo> info;
+  std::vector<HPair> pairs;
+  std::vector<Task> tasks_f, tasks_t;  // 2 per pair: stage 1, stage 2
+  std::vector<LeafItem> l1f, l2f, l1t, l2t;
+  std::vector<RowItem> r1f, r2f, r1t, r2t;
+  std::vector<TermItem> term_items;
+  std::vector<RowItem> gf, gt;  // gather items forward / transposed
+  int64_t vlen = 0, tws_f = 0, tws_t = 0, pair_len = 0;
+  // device
+  DevBuf<TInfo> d_info;
+  DevBuf<HPair> d_pairs;
+  DevBuf<Task> d_tasks_f, d_tasks_t;
+  DevBuf<LeafItem> d_l1f, d_l2f, d_l1t, d_l2t;
+  DevBuf<RowItem> d_r1f, d_r2f, d_r1t, d_r2t, d_gf, d_gt;
+  DevBuf<TermItem> d_terms;
+  DevBuf<double> vbuf, wsf, wst, pairbuf;
+  DevBuf<TDesc> d_td;
+};
+
+int64_t target_cost(const Ctx& c, int32_t b, bool far, const Opts& o, int cap) {
+  const Tree& t = *c.t;
+  int64_t m = c.m_of(b), n = c.n_of(b);
+  int64_t v = 0;
+  for (int32_t a = b; a >= 0; a = t.b_parent[a])
+    for (int32_t i = c.group_ptr_h[a]; i < c.group_ptr_h[a + 1]; ++i)
+      v += int64_t(std::max(c.sym[i].kl, c.sym[i].kr)) * PW;
+  int64_t pr = 0;
+  for (int32_t j = c.hptr[b]; j < c.hptr[b + 1]; ++j) {
+    int32_t rho = c.hrho[j];
+    int32_t qa = t.find_block(t.b_tau[b], rho), qb = t.find_block(rho, t.b_sigma[b]);
+    pr += (t.c_size[rho] + std::max(m, n)) * PW;
+    pr += 2 * (c.da.hkpref[c.dfs.hi[qa]] - c.da.hkpref[c.dfs.lo[qa]] + c.db.hkpref[c.dfs.hi[qb]] -
+               c.db.hkpref[c.dfs.lo[qb]]) * PW;
+  }
+  int64_t panels = far ? (m * (cap + o.o.probes) + n * cap + 2 * cap * cap + cap) : 0;
+  return 8 * (v + pr + panels) + 512;
+}
+
+void build_chunk(const Ctx& c, Chunk& ch) {
+  const Tree& t = *c.t;
+  const int nt = int(ch.blocks.size());
+  ch.info.resize(nt);
+  for (int i = 0; i < nt; ++i) {
+    const int32_t b = ch.blocks[i];
+    TInfo& ti = ch.info[i];
+    ti.block = b;
+    ti.vbase = ch.vlen;
+    for (int32_t a = b; a >= 0; a = t.b_parent[a])
+      for (int32_t j = c.group_ptr_h[a]; j < c.group_ptr_h[a + 1]; ++j) {
+        ch.term_items.push_back(TermItem{i, j, ch.vlen});
+        ch.vlen += int64_t(std::max(c.sym[j].kl, c.sym[j].kr)) * PW;
+      }
+    ti.hp_begin = int32_t(ch.pairs.size());
+    const int32_t tau = t.b_tau[b], sig = t.b_sigma[b];
+    const int32_t m = t.c_size[tau], n = t.c_size[sig];
+    for (int32_t j = c.hptr[b]; j < c.hptr[b + 1]; ++j) {
+      const int32_t rho = c.hrho[j];
+      const int32_t qa = t.find_block(tau, rho), qb = t.find_block(rho, sig);
+      if (qa < 0 || qb < 0) throw Error(HMAT_ERR_INTERNAL, "pair blocks missing");
+      const int64_t off1 = ch.pair_len;
+      ch.pair_len += int64_t(t.c_size[rho]) * PW;
+      const int64_t off2 = ch.pair_len;
+      ch.pair_len += int64_t(std::max(m, n)) * PW;
+      const int32_t p = int32_t(ch.pairs.size());
+      ch.pairs.push_back(HPair{reinterpret_cast<double*>(off2)});  // offset, rebased on upload
+      // forward: stage 1 B[rho, sigma] X -> temp1; stage 2 A[tau, rho] temp1 -> temp2
+      {
+        Task s1{}, s2{};
+        s1.X = nullptr;
+        s1.Y = reinterpret_cast<double*>(off1);
+        s1.ldy = t.c_size[rho];
+        s1.mat = 1;
+        s1.q = qb;
+        s1.trans = 0;
+        s1.t = i;
+        s1.lo = c.dfs.lo[qb];
+        s1.tws = ch.tws_f;
+        ch.tws_f += add_subtree_leaves(c, 2 * p, 1, qb, ch.l1f);
+        add_subtree_rows(t, 2 * p, rho, ch.r1f);
+        s2.X = reinterpret_cast<double*>(off1);
+        s2.ldx = t.c_size[rho];
+        s2.Y = reinterpret_cast<double*>(off2);
+        s2.ldy = m;
+        s2.mat = 0;
+        s2.q = qa;
+        s2.trans = 0;
+        s2.t = i;
+        s2.lo = c.dfs.lo[qa];
+        s2.tws = ch.tws_f;
+        ch.tws_f += add_subtree_leaves(c, 2 * p + 1, 0, qa, ch.l2f);
+        add_subtree_rows(t, 2 * p + 1, tau, ch.r2f);
+        ch.tasks_f.push_back(s1);
+        ch.tasks_f.push_back(s2);
+      }
+      // transposed: stage 1 A[tau, rho]^T X -> temp1; stage 2 B[rho, sigma]^T temp1 -> temp2
+      {
+        Task s1{}, s2{};
+        s1.X = nullptr;
+        s1.Y = reinterpret_cast<double*>(off1);
+        s1.ldy = t.c_size[rho];
+        s1.mat = 0;
+        s1.q = qa;
+        s1.trans = 1;
+        s1.t = i;
+        s1.lo = c.dfs.lo[qa];
+        s1.tws = ch.tws_t;
+        ch.tws_t += add_subtree_leaves(c, 2 * p, 0, qa, ch.l1t);
+        add_subtree_rows(t, 2 * p, rho, ch.r1t);
+        s2.X = reinterpret_cast<double*>(off1);
+        s2.ldx = t.c_size[rho];
+        s2.Y = reinterpret_cast<double*>(off2);
+        s2.ldy = n;
+        s2.mat = 1;
+        s2.q = qb;
+        s2.trans = 1;
+        s2.t = i;
+        s2.lo = c.dfs.lo[qb];
+        s2.tws = ch.tws_t;
+        ch.tws_t += add_subtree_leaves(c, 2 * p + 1, 1, qb, ch.l2t);
+        add_subtree_rows(t, 2 * p + 1, sig, ch.r2t);
+        ch.tasks_t.push_back(s1);
+        ch.tasks_t.push_back(s2);
+      }
+    }
+    ti.hp_end = int32_t(ch.pairs.size());
+    add_subtree_rows(t, i, tau, ch.gf);
+    add_subtree_rows(t, i, sig, ch.gt);
+  }
+}
+
+void upload_chunk(Chunk& ch, hipStream_t s) {
+  ch.pairbuf.alloc(size_t(std::max<int64_t>(ch.pair_len, 1)));
+  double* base = ch.pairbuf.p;
+  auto rebase = [&](double* p) { return base + reinterpret_cast<intptr_t>(p); };
+  for (auto& hp : ch.pairs) hp.temp2 = rebase(hp.temp2);
+  for (auto* tl : {&ch.tasks_f, &ch.tasks_t})
+    for (size_t i = 0; i < tl->size(); ++i) {
+      Task& tk = (*tl)[i];
+      tk.Y = rebase(tk.Y);
+      if (i % 2 == 1) tk.X = rebase(const_cast<double*>(tk.X));
+    }
+  ch.d_info.upload(ch.info, s);
+  ch.d_pairs.upload(ch.pairs, s);
+  ch.d_tasks_f.upload(ch.tasks_f, s);
+  ch.d_tasks_t.upload(ch.tasks_t, s);
+  ch.d_l1f.upload(ch.l1f, s);
+  ch.d_l2f.upload(ch.l2f, s);
+  ch.d_l1t.upload(ch.l1t, s);
+  ch.d_l2t.upload(ch.l2t, s);
+  ch.d_r1f.upload(ch.r1f, s);
+  ch.d_r2f.upload(ch.r2f, s);
+  ch.d_r1t.upload(ch.r1t, s);
+  ch.d_r2t.upload(ch.r2t, s);
+  ch.d_gf.upload(ch.gf, s);
+  ch.d_gt.upload(ch.gt, s);
+  ch.d_terms.upload(ch.term_items, s);
+  ch.vbuf.alloc(size_t(std::max<int64_t>(ch.vlen, 1)));
+  ch.wsf.alloc(size_t(std::max<int64_t>(ch.tws_f, 1)));
+  ch.wst.alloc(size_t(std::max<int64_t>(ch.tws_t, 1)));
+  ch.d_td.alloc(ch.blocks.size());
+}
+
+// One application of every target's operator in the chunk (forward: S X, transposed: S^T X).
+void run_pass(Ctx& c, Chunk& ch, const std::vector<TDesc>& td, bool trans) {
+  hipStream_t s = c.s;
+  ch.d_td.upload(td, s);  // synchronous: td is rewritten for the next pass
+  const TDesc* dtd = ch.d_td.p;
+  launch_term_p1(ch.d_terms.p, ch.term_items.size(), dtd, ch.d_info.p, c.tv, ch.vbuf.p, s);
+  if (!trans) {
+    launch_leaf_p1(ch.d_l1f.p, ch.l1f.size(), ch.d_tasks_f.p, dtd, c.tv, c.ma, c.mb, ch.wsf.p, s);
+    launch_subtree_p2(ch.d_r1f.p, ch.r1f.size(), ch.d_tasks_f.p, dtd, c.tv, c.ma, c.mb, ch.wsf.p, s);
+    launch_leaf_p1(ch.d_l2f.p, ch.l2f.size(), ch.d_tasks_f.p, dtd, c.tv, c.ma, c.mb, ch.wsf.p, s);
+    launch_subtree_p2(ch.d_r2f.p, ch.r2f.size(), ch.d_tasks_f.p, dtd, c.tv, c.ma, c.mb, ch.wsf.p, s);
+    launch_gather(ch.d_gf.p, ch.gf.size(), dtd, ch.d_info.p, ch.d_pairs.p, c.tv, ch.vbuf.p, s);
+  } else {
+    launch_leaf_p1(ch.d_l1t.p, ch.l1t.size(), ch.d_tasks_t.p, dtd, c.tv, c.ma, c.mb, ch.wst.p, s);
+    launch_subtree_p2(ch.d_r1t.p, ch.r1t.size(), ch.d_tasks_t.p, dtd, c.tv, c.ma, c.mb, ch.wst.p, s);
+    launch_leaf_p1(ch.d_l2t.p, ch.l2t.size(), ch.d_tasks_t.p, dtd, c.tv, c.ma, c.mb, ch.wst.p, s);
+    launch_subtree_p2(ch.d_r2t.p, ch.r2t.size(), ch.d_tasks_t.p, dtd, c.tv, c.ma, c.mb, ch.wst.p, s);
+    launch_gather(ch.d_gt.p, ch.gt.size(), dtd, ch.d_info.p, ch.d_pairs.p, c.tv, ch.vbuf.p, s);
+  }
+}
+
+struct FarOut {
+  DevBuf<double> buf;
+  std::vector<int32_t> blocks, ranks;
+  std::vector<int64_t> offs;
+  int64_t len = 0;
+};
+
+// Randomized compression of the chunk's farfield targets.
+void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& out) {
+  const Tree& t = *c.t;
+  hipStream_t s = c.s;
+  const int g = c.opts.o.probes;
+  int b0max = 0;
+  for (int x : w0) b0max = std::max(b0max, x);
+  const int cap = std::min(64, std::max(b0max, c.opts.o.b0) + c.opts.o.max_growth * g);
+  CParams cp{cap, g, c.eps, c.opts.o.delta};
+  const int nt = int(ch.blocks.size());
+  const int64_t ncol_om = std::max(b0max, c.opts.o.b0) + int64_t(g) * (c.opts.o.max_growth + 1);
+  // panels
+  int64_t need = 0;
+  for (int32_t b : ch.blocks) need += int64_t(c.m_of(b)) * (cap + g) + int64_t(c.n_of(b)) * cap + 2 * cap * cap + cap;
+  DevBuf<double> ws{size_t(need)};
+  std::vector<CTarget> h(nt);
+  int64_t o = 0;
+  for (int i = 0; i < nt; ++i) {
+    const int32_t b = ch.blocks[i];
+    CTarget& T = h[i];
+    std::memset(&T, 0, sizeof(T));
+    T.m = c.m_of(b);
+    T.n = c.n_of(b);
+    T.row0 = t.c_begin[t.b_tau[b]];
+    T.col0 = t.c_begin[t.b_sigma[b]];
+    T.Y = ws.p + o;
+    o += int64_t(T.m) * (cap + g);
+    T.Z = ws.p + o;
+    o += int64_t(T.n) * cap;
+    T.core = ws.p + o;
+    o += 2 * cap * cap + cap;
+    T.active = 1;
+    T.block = b;
+    T.w0 = w0[i];
+  }
+  // Gaussian columns shared by all targets (rows keyed by position)
+  DevBuf<double> omega(size_t(t.n) * size_t(ncol_om));
+  launch_fill_gaussian(omega.p, t.n, int32_t(ncol_om), c.opts.o.seed, s);
+  DevBuf<CTarget> dt(nt);
+  dt.upload(h, s);
+  std::vector<TDesc> td(nt);
+  auto clear_td = [&]() {
+    for (auto& d : td) std::memset(&d, 0, sizeof(d));
+  };
+  // forward pass over global columns [j0, j0 + w) of [sketch (w0) | probe (g)]
+  auto sketch_probe = [&](const std::vector<int>& active, int col_probe) {
+    // widths differ per target: run chunks of PW columns over the max total width
+    int maxw = 0;
+    for (int i = 0; i < nt; ++i)
+      if (active[i]) maxw = std::max(maxw, h[i].w0 + g);
+    for (int j0 = 0; j0 < maxw; j0 += PW) {
+      clear_td();
+      bool any = false;
+      for (int i = 0; i < nt; ++i) {
+        if (!active[i]) continue;
+        const CTarget& T = h[i];
+        const int tot = col_probe < 0 ? T.w0 + g : g;
+        if (j0 >= tot) continue;
+        TDesc& d = td[i];
+        d.w = std::min(PW, tot - j0);
+        d.trans = 0;
+        d.ldx = int32_t(t.n);
+        d.ldy = T.m;
+        if (col_probe < 0) {
+          // columns [0, w0) of Omega -> Q area; [w0, w0 + g) -> probe area at cap
+          d.X = omega.p + int64_t(j0) * t.n + T.col0;
+          if (j0 < T.w0) {
+            d.Y = T.Y + int64_t(j0) * T.m;
+            d.split = T.w0 - j0;
+            d.gap = cap - T.w0;
+          } else {
+            d.Y = T.Y + int64_t(j0 - T.w0 + cap) * T.m;
+            d.split = d.w;
+            d.gap = 0;
+          }
+          // probe columns of the first pass come from Omega columns [w0, w0 + g): they are
+          // distinct from the sketch columns by construction
+        } else {
+          d.X = omega.p + int64_t(col_probe + j0) * t.n + T.col0;
+          d.Y = T.Y + int64_t(cap + j0) * T.m;
+          d.split = d.w;
+          d.gap = 0;
+        }
+        any = true;
+      }
+      if (any) run_pass(c, ch, td, false);
+    }
+  };
+  auto project = [&](const std::vector<int>& r_from, const std::vector<int>& r_to) {
+    int maxw = 0;
+    for (int i = 0; i < nt; ++i) maxw = std::max(maxw, r_to[i] - r_from[i]);
+    for (int j0 = 0; j0 < maxw; j0 += PW) {
+      clear_td();
+      bool any = false;
+      for (int i = 0; i < nt; ++i) {
+        const CTarget& T = h[i];
+        const int nw = r_to[i] - r_from[i];
+        if (j0 >= nw) continue;
+        TDesc& d = td[i];
+        d.w = std::min(PW, nw - j0);
+        d.trans = 1;
+        d.X = T.Y + int64_t(r_from[i] + j0) * T.m;
+        d.ldx = T.m;
+        d.Y = T.Z + int64_t(r_from[i] + j0) * T.n;
+        d.ldy = T.n;
+        d.split = d.w;
+        any = true;
+      }
+      if (any) run_pass(c, ch, td, true);
+    }
+  };
+  auto fetch = [&]() {
+    HM_CHECK_HIP(hipMemcpyAsync(h.data(), dt.p, sizeof(CTarget) * nt, hipMemcpyDeviceToHost, s));
+    HM_CHECK_HIP(hipStreamSynchronize(s));
+  };
+  std::vector<int> all(nt, 1);
+  double t0 = now_seconds();
+  sketch_probe(all, -1);
+  // orthonormalise the sketch columns (per-target counts differ: run with the max and let
+  // targets with fewer columns see zero-width extra columns)
+  {
+    int maxw0 = 0;
+    for (auto& T : h) maxw0 = std::max(maxw0, T.w0);
+    launch_orth_append(dt.p, nt, 0, maxw0, cp, s);  // each target uses its own w0 columns
+  }
+  launch_probe_residual(dt.p, nt, cp, s);
+  fetch();
+  double t1 = now_seconds();
+  c.st.t_sketch += t1 - t0;
+  std::vector<int> rf(nt, 0), rt(nt);
+  for (int i = 0; i < nt; ++i) rt[i] = h[i].r;
+  project(rf, rt);
+  for (auto& T : h) T.rz = T.r;
+  dt.upload(h, s);
+  double t2 = now_seconds();
+  c.st.t_project += t2 - t1;
+  DevBuf<int32_t> pending(nt);
+  std::vector<int32_t> hp(nt);
+  for (auto& T : h) c.st.sketch_columns += T.w0;
+  for (int round = 0; round < c.opts.o.max_growth; ++round) {
+    launch_check(dt.p, nt, cp, pending.p, s);
+    HM_CHECK_HIP(hipMemcpyAsync(hp.data(), pending.p, 4 * nt, hipMemcpyDeviceToHost, s));
+    fetch();
+    int cnt = 0;
+    for (int i = 0; i < nt; ++i) {
+      h[i].active = hp[i];
+      cnt += hp[i];
+    }
+    if (!cnt) break;
+    c.st.n_growth_rounds++;
+    c.st.n_grown_blocks += cnt;
+    double ta = now_seconds();
+    dt.upload(h, s);
+    std::vector<int> r_old(nt);
+    for (int i = 0; i < nt; ++i) r_old[i] = h[i].r;
+    launch_orth_append(dt.p, nt, cap, g, cp, s);
+    fetch();
+    std::vector<int> act(nt);
+    for (int i = 0; i < nt; ++i) {
+      act[i] = h[i].active;
+      if (act[i]) {
+        h[i].rounds++;
+        c.st.sketch_columns += g;
+      }
+    }
+    // next probe columns of Omega: [w0 + g * (round + 1), ...) keyed per round
+    sketch_probe(act, std::max(b0max, c.opts.o.b0) + g * (round + 1));
+    double tb = now_seconds();
+    c.st.t_sketch += tb - ta;
+    std::vector<int> rto(nt);
+    for (int i = 0; i < nt; ++i) rto[i] = act[i] ? h[i].r : r_old[i];
+    for (int i = 0; i < nt; ++i)
+      if (!act[i]) r_old[i] = rto[i];
+    project(r_old, rto);
+    for (int i = 0; i < nt; ++i) h[i].rz = h[i].r;
+    dt.upload(h, s);
+    launch_probe_residual(dt.p, nt, cp, s);
+    c.st.t_project += now_seconds() - tb;
+  }
+  double t3 = now_seconds();
+  launch_check(dt.p, nt, cp, pending.p, s);
+  launch_core(dt.p, nt, cp, s);
+  fetch();
+  out.blocks.clear();
+  out.ranks.clear();
+  out.offs.clear();
+  out.len = 0;
+  for (int i = 0; i < nt; ++i) {
+    CTarget& T = h[i];
+    if (!T.done) c.st.n_not_converged++;
+    out.blocks.push_back(T.block);
+    out.ranks.push_back(T.k);
+    out.offs.push_back(out.len);
+    T.out_off = out.len;
+    out.len += int64_t(T.k) * (T.m + T.n);
+    c.st.rank_hist[std::min(T.k, 64)]++;
+  }
+  out.buf.alloc(size_t(std::max<int64_t>(out.len, 1)));
+  dt.upload(h, s);
+  launch_write_factors(dt.p, nt, cp, out.buf.p, s);
+  HM_CHECK_HIP(hipStreamSynchronize(s));
+  c.st.t_core += now_seconds() - t3;
+}
+
+// Nearfield targets: S applied to the identity, PW columns at a time, straight into C.
+void evaluate_chunk(Ctx& c, Chunk& ch, double* cpool, const std::vector<int64_t>& coff) {
+  const Tree& t = *c.t;
+  const int nt = int(ch.blocks.size());
+  int maxn = 0;
+  for (int32_t b : ch.blocks) maxn = std::max(maxn, c.n_of(b));
+  std::vector<TDesc> td(nt);
+  for (int j0 = 0; j0 < maxn; j0 += PW) {
+    for (int i = 0; i < nt; ++i) {
+      TDesc& d = td[i];
+      std::memset(&d, 0, sizeof(d));
+      const int32_t b = ch.blocks[i];
+      const int n = c.n_of(b), m = c.m_of(b);
+      if (j0 >= n) continue;
+      d.w = std::min(PW, n - j0);
+      d.trans = 0;
+      d.xident = 1;
+      d.xcol0 = j0;
+      d.X = nullptr;
+      d.Y = cpool + coff[i] + int64_t(j0) * m;
+      d.ldy = m;
+      d.split = d.w;
+    }
+    run_pass(c, ch, td, false);
+  }
+  HM_CHECK_HIP(hipStreamSynchronize(c.s));
+  (void)t;
+}
+
+}  // namespace
+
+hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout) {
+  const double t_start = now_seconds();
+  HM_REQUIRE(A->tree == B->tree, HMAT_ERR_TREE_MISMATCH, "A and B must be built on the same tree");
+  Tree* t = A->tree;
+  HM_REQUIRE(t->leaf_size <= 64, HMAT_ERR_ARG, "the product needs leaf_size <= 64");
+  for (int32_t b : t->leaves)
+    if (t->b_kind[b] == KIND_F)
+      HM_REQUIRE(A->rank[b] <= 64 && B->rank[b] <= 64, HMAT_ERR_ARG, "input ranks above 64 are not supported");
+  Ctx c;
+  c.t = t;
+  c.A = A;
+  c.B = B;
+  c.s = opts.stream();
+  c.eps = eps;
+  c.opts = opts;
+  hipStream_t s = c.s;
+  t->ensure_device(s);
+
+  // plan
+  c.dfs = dfs_order(*t);
+  build_kpref(A, c.dfs, c.da, s);
+  build_kpref(B, c.dfs, c.db, s);
+  c.ma = c.da.view(A);
+  c.mb = c.db.view(B);
+  symbolic(c);
+  c.b_parent.upload(t->b_parent, s);
+  c.b_dfs.upload(c.dfs.dfs_of_block, s);
+  c.group_ptr.upload(c.group_ptr_h, s);
+  c.hterms.assign(c.sym.size(), Term{});
+  c.tv = TreeView{t->dev->c_begin.p, t->dev->c_size.p, t->dev->c_parent.p, t->dev->leaf_clusters.p,
+                  t->dev->b_tau.p, t->dev->b_sigma.p, t->dev->b_kind.p, c.b_parent.p, c.b_dfs.p,
+                  t->dev->brow_ptr.p, t->dev->brow_blk.p, t->dev->bcol_ptr.p, t->dev->bcol_blk.p,
+                  c.group_ptr.p, nullptr};
+  c.st.t_plan = now_seconds() - t_start;
+
+  // creation of all terms
+  double tc = now_seconds();
+  std::vector<int32_t> all_terms(c.sym.size());
+  std::iota(all_terms.begin(), all_terms.end(), 0);
+  DevBuf<double> term_pool;
+  create_terms(c, all_terms, term_pool);
+  c.terms.upload(c.hterms, s);
+  c.tv.terms = c.terms.p;
+  HM_CHECK_HIP(hipStreamSynchronize(s));
+  c.st.t_restrict = now_seconds() - tc;
+
+  // output matrix
+  HMat* C = new HMat();
+  C->tree = t;
+  tree_retain(t);
+  const int64_t nb = int64_t(t->b_tau.size());
+  C->rank.assign(nb, 0);
+  C->off.assign(nb, -1);
+  std::vector<int32_t> far, near;
+  for (int32_t b : t->leaves) (t->b_kind[b] == KIND_F ? far : near).push_back(b);
+  c.st.n_far = int64_t(far.size());
+  c.st.n_near = int64_t(near.size());
+  int64_t near_len = 0;
+  std::vector<int64_t> near_off(nb, -1);
+  for (int32_t b : near) {
+    near_off[b] = near_len;
+    near_len += int64_t(c.m_of(b)) * c.n_of(b);
+  }
+  DevBuf<double> near_buf(size_t(std::max<int64_t>(near_len, 1)));
+
+  const int64_t budget = opts.o.workspace_limit > 0 ? opts.o.workspace_limit : (int64_t(3) << 30);
+  const int cap_est = std::min(64, opts.o.b0 + opts.o.max_growth * opts.o.probes);
+  // nearfield evaluation
+  double tn = now_seconds();
+  for (size_t i = 0; i < near.size();) {
+    Chunk ch;
+    int64_t used = 0;
+    while (i < near.size()) {
+      int64_t cst = target_cost(c, near[i], false, opts, cap_est);
+      if (!ch.blocks.empty() && used + cst > budget) break;
+      used += cst;
+      ch.blocks.push_back(near[i++]);
+    }
+    build_chunk(c, ch);
+    upload_chunk(ch, s);
+    std::vector<int64_t> coff;
+    for (int32_t b : ch.blocks) coff.push_back(near_off[b]);
+    evaluate_chunk(c, ch, near_buf.p, coff);
+  }
+  c.st.t_near = now_seconds() - tn;
+
+  // farfield compression
+  std::vector<FarOut> outs;
+  for (size_t i = 0; i < far.size();) {
+    Chunk ch;
+    int64_t used = 0;
+    while (i < far.size()) {
+      int64_t cst = target_cost(c, far[i], true, opts, cap_est);
+      if (!ch.blocks.empty() && used + cst > budget) break;
+      used += cst;
+      ch.blocks.push_back(far[i++]);
+    }
+    build_chunk(c, ch);
+    upload_chunk(ch, s);
+    std::vector<int32_t> w0(ch.blocks.size(), opts.o.b0);
+    outs.emplace_back();
+    compress_chunk(c, ch, w0, outs.back());
+  }
+
+  // assemble C's pool: nearfield blocks, then farfield chunks
+  int64_t total = near_len;
+  std::vector<int64_t> base;
+  for (auto& o : outs) {
+    base.push_back(total);
+    total += o.len;
+  }
+  C->pool_len = total;
+  C->pool.alloc(size_t(std::max<int64_t>(total, 1)));
+  if (near_len)
+    HM_CHECK_HIP(hipMemcpyAsync(C->pool.p, near_buf.p, 8 * near_len, hipMemcpyDeviceToDevice, s));
+  for (int32_t b : near) C->off[b] = near_off[b];
+  for (size_t k = 0; k < outs.size(); ++k) {
+    auto& o = outs[k];
+    if (o.len) HM_CHECK_HIP(hipMemcpyAsync(C->pool.p + base[k], o.buf.p, 8 * o.len, hipMemcpyDeviceToDevice, s));
+    for (size_t j = 0; j < o.blocks.size(); ++j) {
+      C->rank[o.blocks[j]] = o.ranks[j];
+      C->off[o.blocks[j]] = base[k] + o.offs[j];
+    }
+  }
+  C->upload_meta(s);
+  HM_CHECK_HIP(hipStreamSynchronize(s));
+  c.st.t_total = now_seconds() - t_start;
+  if (opts.o.stats) *opts.o.stats = c.st;
+  *Cout = C;
+  if (c.st.n_not_converged > 0) {
+    set_last_error(std::to_string(c.st.n_not_converged) + " farfield blocks exhausted the growth budget");
+    return HMAT_ERR_NOT_CONVERGED;
+  }
+  return HMAT_OK;
+}
+
+hmat_status multiply_batched(HMat* const* A, HMat* const* B, int32_t count, double eps, const Opts& opts,
+                             HMat** C, int32_t* status) {
+  hmat_status worst = HMAT_OK;
+  for (int32_t i = 0; i < count; ++i) {
+    C[i] = nullptr;
+    hmat_status st;
+    try {
+      st = multiply(A[i], B[i], eps, opts, &C[i]);
+    } catch (const Error& e) {
+      set_last_error(e.what());
+      st = e.code;
+    }
+    if (status) status[i] = st;
+    if (st != HMAT_OK && worst == HMAT_OK) worst = st;
+  }
+  return worst;
+}
+
+}  // namespace hm

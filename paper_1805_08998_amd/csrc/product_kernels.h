@@ -1,0 +1,106 @@
+// Device-side data of the product: low-rank terms of the sum-expressions,
+// subtree product tasks, per-target pass descriptors and work items.
+#pragma once
+
+#include <cstdint>
+
+namespace hm {
+
+constexpr int PW = 16;  // columns per apply pass (wider passes are split)
+
+// One low-rank term of a sum-expression, L * core * R^T (Def. 3.1), stored
+// through views into the factor pools. Restriction to a sub-block (Algorithm 3)
+// is an index shift: row position p of the target maps to panel row p - lrow0.
+struct Term {
+  const double* L;     // element (i, c) at L[i + c * ldl]
+  const double* R;     // rtrans == 0: (j, c) at R[j + c * ldr]; rtrans == 1: at R[c + j * ldr]
+  const double* core;  // kl x kr column-major (ld kl), or null when kl == kr and the core is I
+  int32_t ldl, ldr;
+  int32_t lrow0, rrow0;
+  int32_t kl, kr;
+  int32_t rtrans, pad;
+};
+
+struct MatView {
+  const double* pool;
+  const int32_t* rank;   // per block
+  const int64_t* off;    // per block, element offset of the leaf data in pool
+  const int64_t* kpref;  // per depth-first leaf index: prefix sum of farfield ranks
+};
+
+struct TreeView {
+  const int32_t* c_begin;
+  const int32_t* c_size;
+  const int32_t* c_parent;
+  const int32_t* leaf_clusters;
+  const int32_t* b_tau;
+  const int32_t* b_sigma;
+  const int32_t* b_kind;
+  const int32_t* b_parent;
+  const int32_t* b_dfs;  // depth-first leaf index of a leaf block
+  const int32_t* brow_ptr;
+  const int32_t* brow_blk;
+  const int32_t* bcol_ptr;
+  const int32_t* bcol_blk;
+  const int32_t* group_ptr;  // terms created at each block
+  const Term* terms;
+};
+
+// Pass descriptor of one target: the target's operator is applied to X
+// (forward: S X with X rows = sigma, output rows = tau; transposed: S^T X with
+// X rows = tau, output rows = sigma). w == 0 marks an inactive target.
+struct TDesc {
+  const double* X;
+  double* Y;
+  int32_t ldx, ldy;
+  int32_t w;
+  int32_t split, gap;  // output column j goes to j (j < split) or j + gap
+  int32_t trans;
+  int32_t xident;      // X is the identity restricted to columns [xcol0, xcol0 + w)
+  int32_t xcol0, pad;
+};
+
+struct TInfo {
+  int32_t block;
+  int32_t hp_begin, hp_end;  // H-pairs of the target
+  int32_t pad;
+  int64_t vbase;             // first slot of the target's term results
+};
+
+// Product of a subtree of A or B with a panel: trans == 0: Y[tau_q] = M[q] X[sigma_q];
+// trans == 1: Y[sigma_q] = M[q]^T X[tau_q]. When t >= 0 the width and, if X is
+// null, the input come from the target's pass descriptor.
+struct Task {
+  const double* X;
+  double* Y;
+  int32_t ldx, ldy;
+  int32_t mat;  // 0 = A, 1 = B
+  int32_t q;
+  int32_t trans;
+  int32_t t;
+  int32_t w;    // fixed width when t < 0
+  int32_t lo;   // first depth-first leaf index of subtree(q)
+  int64_t tws;  // workspace of the leaf products R^T X (or L^T X)
+};
+
+struct TermItem {
+  int32_t t, term;
+  int64_t voff;
+};
+
+struct LeafItem {
+  int32_t task, block;
+};
+
+struct RowItem {  // output rows: leaf cluster lc (index into leaf_clusters), 64-row chunk
+  int32_t owner;  // task or target
+  int32_t lc;
+  int32_t chunk;
+  int32_t pad;
+};
+
+struct HPair {
+  double* temp2;  // output of the second stage (rows of the target's output cluster, ld = its size)
+};
+
+}  // namespace hm

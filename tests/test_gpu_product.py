@@ -1,0 +1,87 @@
+"""GPU product vs the oracle's exact blocks (brute force, small n).
+
+Farfield blocks: relative Frobenius error <= 1.01 eps and rank <= eps-rank + 2.
+Nearfield blocks: relative error <= 1e-12. The oracle ingests the library's own
+exported A and B, so input compression errors cancel out of the comparison.
+"""
+
+import numpy as np
+import pytest
+
+from workloads import fibonacci_sphere, jitter, cube_surface
+from oracle.product import brute_force_product, check_block
+from oracle.hmatrix import KIND_F
+from tests.helpers import exported_to_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_1805_08998_amd import hmat
+    hmat.lib()
+    return hmat
+
+
+def run_case(H, pts, leaf, split, ka, kb, eps, same=False, opts=None):
+    t = H.hmat_build_tree(pts, leaf, 0.8, split)
+    A, _ = H.hmat_assemble(t, *ka, eps_in=1e-8)
+    B = A if same else H.hmat_assemble(t, *kb, eps_in=1e-8)[0]
+    st = H.hmat_stats()
+    o = opts or H.hmat_opts_default()
+    import ctypes
+    o.stats = ctypes.pointer(st)
+    C, code = H.hmat_multiply(A, B, eps, o)
+    Ao = exported_to_oracle(H, t, A)
+    Bo = Ao if same else exported_to_oracle(H, t, B)
+    Co = exported_to_oracle(H, t, C)
+    P = brute_force_product(Ao, Bo)
+    worst_f, worst_n, slack, nbad = 0.0, 0.0, -99, 0
+    for lf in Co.leaves:
+        D = P[lf.r0:lf.r0 + lf.m, lf.c0:lf.c0 + lf.n]
+        if lf.kind == KIND_F:
+            r = check_block(D, KIND_F, eps, U=lf.L, V=lf.R)
+            worst_f = max(worst_f, r.err)
+            slack = max(slack, r.rank - r.kstar)
+        else:
+            r = check_block(D, 2, eps, Dc=lf.D)
+            worst_n = max(worst_n, r.err)
+        nbad += (not r.ok)
+    for h in ([A, C] if same else [A, B, C]):
+        H.hmat_destroy(h)
+    H.hmat_tree_destroy(t)
+    print(f"far worst {worst_f:.3e} (eps {eps}), rank-k* max {slack}, near worst {worst_n:.3e}, "
+          f"bad {nbad}, growth rounds {st.n_growth_rounds}, not conv {st.n_not_converged}", flush=True)
+    return nbad, worst_f, worst_n, code
+
+
+@pytest.mark.parametrize("name,n,leaf,split", [
+    ("sphere2k-laplace", 2048, 32, 0),
+    ("sphere1500-median", 1500, 24, 1),
+])
+def test_product_laplace_square(H, name, n, leaf, split):
+    print(f"[product] {name}", flush=True)
+    pts = fibonacci_sphere(n)
+    nbad, wf, wn, code = run_case(H, pts, leaf, split, ("laplace_4pi", 1.0, 0.0), None, 1e-6, same=True)
+    assert code == 0 and nbad == 0
+
+
+def test_product_mixed_kernels(H):
+    print("[product] jittered sphere 3000, laplace x (exp + I)", flush=True)
+    pts = jitter(fibonacci_sphere(3000), 1e-3, 0)
+    nbad, wf, wn, code = run_case(H, pts, 48, 0, ("laplace_4pi", 1.0, 0.0), ("exp", 1.0, 1.0), 1e-6)
+    assert code == 0 and nbad == 0
+
+
+def test_product_cube_eps4(H):
+    print("[product] cube 2500, 1/r x exp, eps 1e-4", flush=True)
+    pts = cube_surface(2500, 1)
+    nbad, wf, wn, code = run_case(H, pts, 32, 0, ("inv_dist", 1.0, 0.0), ("exp", 1.0, 0.0), 1e-4)
+    assert code == 0 and nbad == 0
+
+
+def test_product_root_is_leaf(H):
+    print("[product] n = 40 with leaf 64 (single dense block)", flush=True)
+    pts = fibonacci_sphere(40)
+    nbad, wf, wn, code = run_case(H, pts, 64, 0, ("exp", 1.0, 0.0), ("inv_dist", 1.0, 0.0), 1e-6)
+    assert code == 0 and nbad == 0
