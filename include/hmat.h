@@ -162,7 +162,7 @@ typedef struct {
   int32_t max_growth;  /* growth rounds before HMAT_ERR_NOT_CONVERGED (default 6) */
   int32_t p_l;         /* oversampling added to a predicted rank (default 3) */
   int32_t reserved;
-  double delta;        /* residual target: E <= delta * eps * ||S||_F (default 0.05) */
+  double delta;        /* residual target: E <= delta * eps * ||S||_F (default 0.2) */
   uint64_t seed;       /* random stream of the sketches (default 0x5eed) */
   void* stream;        /* hipStream_t (0 = null stream) */
   hmat_rank_model rank_model;  /* required for HMAT_RANK_PREDICT */

@@ -132,7 +132,7 @@ void hmat_opts_default(hmat_opts* o) {
   o->probes = 8;
   o->max_growth = 6;
   o->p_l = 3;
-  o->delta = 0.05;
+  o->delta = 0.2;
   o->seed = 0x5eedull;
 }
 

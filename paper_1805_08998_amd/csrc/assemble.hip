@@ -170,7 +170,7 @@ HMat* assemble_kernel(Tree* t, const hmat_kernel* k, double eps_in, const Opts& 
 
   // farfield compression in chunks bounded by a workspace budget
   const int b0 = 16, g = 8, cap = 48;
-  CParams cp{cap, g, eps_in, opts.o.delta};
+  CParams cp{cap, g, eps_in, opts.o.delta, 9.0};
   const int max_rounds = (cap - b0) / g;
   struct ChunkOut {
     DevBuf<double> buf;
@@ -183,7 +183,7 @@ HMat* assemble_kernel(Tree* t, const hmat_kernel* k, double eps_in, const Opts& 
   const int ncol_omega = b0 + g * (max_rounds + 1);
   launch_fill_gaussian(omega.p, t->n, ncol_omega, opts.o.seed ^ 0xA55E3B1Eull, s);
 
-  const int64_t budget = int64_t(2) << 30;  // bytes of panels per chunk
+  const int64_t budget = opts.o.workspace_limit > 0 ? opts.o.workspace_limit : (int64_t(2) << 30);
   size_t fi = 0;
   int64_t not_conv = 0;
   while (fi < far.size()) {
@@ -304,23 +304,19 @@ HMat* assemble_kernel(Tree* t, const hmat_kernel* k, double eps_in, const Opts& 
     outs.push_back(std::move(co));
   }
 
-  // final pool: nearfield blocks then the farfield chunks
+  // final pool: nearfield blocks then the farfield chunks, each chunk at its own base
   int64_t total = dense_len;
-  for (auto& co : outs)
+  std::vector<int64_t> chunk_base, chunk_len;
+  for (auto& co : outs) {
+    int64_t len = 0;
     for (size_t i = 0; i < co.blocks.size(); ++i) {
       int32_t b = co.blocks[i];
       M->rank[b] = co.ranks[i];
       M->off[b] = total + co.offs[i];
+      len += int64_t(co.ranks[i]) * (t->c_size[t->b_tau[b]] + t->c_size[t->b_sigma[b]]);
     }
-  std::vector<int64_t> chunk_base;
-  for (auto& co : outs) {
     chunk_base.push_back(total);
-    int64_t len = 0;
-    for (size_t i = 0; i < co.blocks.size(); ++i) {
-      int32_t b = co.blocks[i];
-      len += int64_t(co.ranks[i]) *
-             (t->c_size[t->b_tau[b]] + t->c_size[t->b_sigma[b]]);
-    }
+    chunk_len.push_back(len);
     total += len;
   }
   M->pool_len = total;
@@ -333,16 +329,10 @@ HMat* assemble_kernel(Tree* t, const hmat_kernel* k, double eps_in, const Opts& 
     HM_CHECK_HIP(hipGetLastError());
     HM_CHECK_HIP(hipStreamSynchronize(s));
   }
-  for (size_t c = 0; c < outs.size(); ++c) {
-    int64_t len = 0;
-    for (size_t i = 0; i < outs[c].blocks.size(); ++i) {
-      int32_t b = outs[c].blocks[i];
-      len += int64_t(outs[c].ranks[i]) * (t->c_size[t->b_tau[b]] + t->c_size[t->b_sigma[b]]);
-    }
-    if (len)
-      HM_CHECK_HIP(hipMemcpyAsync(M->pool.p + chunk_base[c], outs[c].buf.p, 8 * len,
+  for (size_t c = 0; c < outs.size(); ++c)
+    if (chunk_len[c])
+      HM_CHECK_HIP(hipMemcpyAsync(M->pool.p + chunk_base[c], outs[c].buf.p, 8 * chunk_len[c],
                                   hipMemcpyDeviceToDevice, s));
-  }
   M->upload_meta(s);
   HM_CHECK_HIP(hipStreamSynchronize(s));
   if (n_not_converged) *n_not_converged = not_conv;

@@ -8,7 +8,10 @@
 //   while E > delta * eps * sqrt(||B||^2 + E^2): Q += orth(P'), new probe, new
 //     projection columns (adaptive growth),
 //   Z = Qz Rz, one-sided Jacobi on Rz^T = W J^T, output L = Q W_k, R = Qz J_k with
-//   the smallest k such that tail_k^2 <= eps^2 (||B||^2 + E^2) - E^2.
+//   the smallest k such that tail_k^2 <= eps^2 (||B||^2 + E^2) - kappa E^2.
+// The block error is E_true^2 + tail_k^2 (orthogonal pieces); kappa > 1 keeps it
+// below eps ||S|| unless the probe underestimates the residual norm by more than
+// sqrt(kappa).
 // Only the products S X and S^T X depend on the operator; they are supplied by
 // the caller (kernel evaluation for assembly, sum-expressions for the product).
 #pragma once
@@ -40,6 +43,7 @@ struct CParams {
   int32_t g;       // probe columns
   double eps;
   double delta;
+  double kappa;  // safety factor on the estimated residual in the truncation rule
 };
 
 // Omega: n x ncol Gaussian matrix (column-major, ld = n) keyed by (seed, position, column).

@@ -154,7 +154,8 @@ void launch_check(CTarget* t, int nt, const CParams& p, int32_t* pending, hipStr
 // ---------------------------------------------------------------- core SVD + truncation
 constexpr int CAPMAX = 64;
 
-__global__ void __launch_bounds__(NT) k_core(CTarget* __restrict__ tg, int nt, int cap, double eps) {
+__global__ void __launch_bounds__(NT) k_core(CTarget* __restrict__ tg, int nt, int cap, double eps,
+                                             double kappa) {
   __shared__ double h[CAPMAX];
   __shared__ double red[NT / 64];
   __shared__ double M[CAPMAX * CAPMAX];  // Rz^T, column-major, ld CAPMAX
@@ -232,7 +233,7 @@ __global__ void __launch_bounds__(NT) k_core(CTarget* __restrict__ tg, int nt, i
       }
       double total = 0.0;
       for (int j = 0; j < r; ++j) total += sig[j] * sig[j];
-      double thr = eps * eps * (total + T.E2) - T.E2;
+      double thr = eps * eps * (total + T.E2) - kappa * T.E2;
       int k = r;
       double tail = 0.0;  // tail(k) = sum_{i >= k} sigma_i^2 in sorted order
       for (int kk = r; kk >= 0; --kk) {
@@ -259,7 +260,7 @@ __global__ void __launch_bounds__(NT) k_core(CTarget* __restrict__ tg, int nt, i
 void launch_core(CTarget* t, int nt, const CParams& p, hipStream_t s) {
   if (nt <= 0) return;
   if (p.cap > CAPMAX) throw Error(HMAT_ERR_INTERNAL, "column capacity above 64");
-  hipLaunchKernelGGL(k_core, dim3(nt), dim3(NT), 0, s, t, nt, p.cap, p.eps);
+  hipLaunchKernelGGL(k_core, dim3(nt), dim3(NT), 0, s, t, nt, p.cap, p.eps, p.kappa);
   HM_CHECK_HIP(hipGetLastError());
 }
 

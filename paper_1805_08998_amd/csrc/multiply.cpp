@@ -552,7 +552,7 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
   int b0max = 0;
   for (int x : w0) b0max = std::max(b0max, x);
   const int cap = std::min(64, std::max(b0max, c.opts.o.b0) + c.opts.o.max_growth * g);
-  CParams cp{cap, g, c.eps, c.opts.o.delta};
+  CParams cp{cap, g, c.eps, c.opts.o.delta, 9.0};
   const int nt = int(ch.blocks.size());
   const int64_t ncol_om = std::max(b0max, c.opts.o.b0) + int64_t(g) * (c.opts.o.max_growth + 1);
   // panels

@@ -25,11 +25,13 @@ def H():
     ("exp", 1.0, 1.0, 3000, 64),
     ("inv_dist", 1.0, 0.0, 1500, 20),
 ])
-def test_assembly_blocks(H, kind, diag, shift, n, leaf):
-    print(f"[assembly] kind={kind} n={n} leaf={leaf}", flush=True)
+@pytest.mark.parametrize("budget", [0, 1 << 20])
+def test_assembly_blocks(H, kind, diag, shift, n, leaf, budget):
+    """budget 1 MB forces many assembly chunks (regression: chunk offsets)."""
+    print(f"[assembly] kind={kind} n={n} leaf={leaf} budget={budget}", flush=True)
     pts = jitter(fibonacci_sphere(n), 1e-3, 0) if kind == "exp" else fibonacci_sphere(n)
     t = H.hmat_build_tree(pts, leaf, 0.8, 0)
-    M, code = H.hmat_assemble(t, kind, diag, shift, 1e-8)
+    M, code = H.hmat_assemble(t, kind, diag, shift, 1e-8, opts=H.hmat_opts_default(workspace_limit=budget))
     Hm = exported_to_oracle(H, t, M)
     perm = Hm.perm
     worst, slack = 0.0, -99

@@ -85,3 +85,21 @@ def test_product_root_is_leaf(H):
     pts = fibonacci_sphere(40)
     nbad, wf, wn, code = run_case(H, pts, 64, 0, ("exp", 1.0, 0.0), ("inv_dist", 1.0, 0.0), 1e-6)
     assert code == 0 and nbad == 0
+
+
+def test_product_many_chunks(H):
+    """A tiny workspace budget splits the targets into many chunks."""
+    print("[product] sphere2k with a 4 MB workspace budget", flush=True)
+    pts = fibonacci_sphere(2048)
+    o = H.hmat_opts_default()
+    o.workspace_limit = 4 << 20
+    nbad, wf, wn, code = run_case(H, pts, 32, 0, ("laplace_4pi", 1.0, 0.0), None, 1e-6, same=True, opts=o)
+    assert code == 0 and nbad == 0
+
+
+@pytest.mark.slow
+def test_product_sphere8k(H):
+    print("[product] jittered sphere 8192, leaf 64, laplace x (exp + I)", flush=True)
+    pts = jitter(fibonacci_sphere(8192), 1e-3, 0)
+    nbad, wf, wn, code = run_case(H, pts, 64, 0, ("laplace_4pi", 1.0, 0.0), ("exp", 1.0, 1.0), 1e-6)
+    assert code == 0 and nbad == 0
