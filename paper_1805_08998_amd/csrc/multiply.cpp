@@ -113,6 +113,8 @@ struct Ctx {
   hmat_stats st{};
   double eps;
   Opts opts;
+  DevBuf<double> omega;  // Gaussian columns shared by all targets, rows keyed by position
+  int64_t omega_cols = 0;
 
   int32_t m_of(int32_t b) const { return t->c_size[t->b_tau[b]]; }
   int32_t n_of(int32_t b) const { return t->c_size[t->b_sigma[b]]; }
@@ -579,9 +581,13 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
     T.block = b;
     T.w0 = w0[i];
   }
-  // Gaussian columns shared by all targets (rows keyed by position)
-  DevBuf<double> omega(size_t(t.n) * size_t(ncol_om));
-  launch_fill_gaussian(omega.p, t.n, int32_t(ncol_om), c.opts.o.seed, s);
+  // Gaussian columns shared by all targets (rows keyed by position), generated once
+  if (c.omega_cols < ncol_om) {
+    c.omega.alloc(size_t(t.n) * size_t(ncol_om));
+    launch_fill_gaussian(c.omega.p, t.n, int32_t(ncol_om), c.opts.o.seed, s);
+    c.omega_cols = ncol_om;
+  }
+  const double* omega_p = c.omega.p;
   DevBuf<CTarget> dt(nt);
   dt.upload(h, s);
   std::vector<TDesc> td(nt);
@@ -609,7 +615,7 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
         d.ldy = T.m;
         if (col_probe < 0) {
           // columns [0, w0) of Omega -> Q area; [w0, w0 + g) -> probe area at cap
-          d.X = omega.p + int64_t(j0) * t.n + T.col0;
+          d.X = omega_p + int64_t(j0) * t.n + T.col0;
           if (j0 < T.w0) {
             d.Y = T.Y + int64_t(j0) * T.m;
             d.split = T.w0 - j0;
@@ -622,7 +628,7 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
           // probe columns of the first pass come from Omega columns [w0, w0 + g): they are
           // distinct from the sketch columns by construction
         } else {
-          d.X = omega.p + int64_t(col_probe + j0) * t.n + T.col0;
+          d.X = omega_p + int64_t(col_probe + j0) * t.n + T.col0;
           d.Y = T.Y + int64_t(cap + j0) * T.m;
           d.split = d.w;
           d.gap = 0;
@@ -814,73 +820,163 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
                   c.group_ptr.p, nullptr};
   c.st.t_plan = now_seconds() - t_start;
 
-  // creation of all terms
-  double tc = now_seconds();
-  std::vector<int32_t> all_terms(c.sym.size());
-  std::iota(all_terms.begin(), all_terms.end(), 0);
-  DevBuf<double> term_pool;
-  create_terms(c, all_terms, term_pool);
-  c.terms.upload(c.hterms, s);
-  c.tv.terms = c.terms.p;
-  HM_CHECK_HIP(hipStreamSynchronize(s));
-  c.st.t_restrict = now_seconds() - tc;
+  // memory of the data each term creates, and the level of the block it belongs to
+  const int64_t nsym = int64_t(c.sym.size());
+  std::vector<int64_t> tmem(nsym);
+  for (int64_t i = 0; i < nsym; ++i) {
+    const SymTerm& st = c.sym[i];
+    tmem[i] = st.type == T_FF ? int64_t(st.kl) * st.kr
+            : st.type == T_FH ? int64_t(st.kl) * c.n_of(st.child)
+            : st.type == T_HF ? int64_t(st.kl) * c.m_of(st.child) : 0;
+    tmem[i] *= 8;
+  }
+  // Subtree batches: terms of blocks deeper than level L0 live only while the targets
+  // of their level-L0 subtree group are processed (the paper's recursion is depth
+  // first; this is the same order at the granularity of a batch of subtrees).
+  int64_t term_budget;
+  {
+    size_t fb = 0, tb = 0;
+    HM_CHECK_HIP(hipMemGetInfo(&fb, &tb));
+    term_budget = opts.o.workspace_limit > 0 ? 8 * opts.o.workspace_limit : int64_t(0.45 * double(fb));
+  }
+  const int depth = t->depth;
+  std::vector<int64_t> cum(depth + 2, 0);
+  for (int64_t i = 0; i < nsym; ++i) cum[t->b_level[c.sym[i].child]] += tmem[i];
+  for (int l = 1; l <= depth + 1; ++l) cum[l] += cum[l - 1];
+  int L0 = depth;
+  if (cum[depth] > term_budget) {
+    L0 = 0;
+    for (int l = 0; l <= depth; ++l)
+      if (cum[l] <= term_budget / 4) L0 = l;
+  }
+  const int64_t nb = int64_t(t->b_tau.size());
+  std::vector<int32_t> root0(nb, -1);  // level-L0 ancestor of blocks at levels >= L0
+  for (int64_t b = 0; b < nb; ++b) {
+    if (t->b_level[b] == L0) root0[b] = int32_t(b);
+    else if (t->b_level[b] > L0) root0[b] = root0[t->b_parent[b]];
+  }
+  // group level-L0 blocks into batches by the memory of their subtrees' terms
+  std::vector<int64_t> sub_mem(nb, 0);
+  for (int64_t i = 0; i < nsym; ++i) {
+    int32_t ch = c.sym[i].child;
+    if (t->b_level[ch] > L0) sub_mem[root0[ch]] += tmem[i];
+  }
+  std::vector<int32_t> batch_of(nb, -1);
+  int nbatch = 0;
+  {
+    int64_t used = 0;
+    const int64_t room = std::max<int64_t>(term_budget - cum[std::min(L0, depth)], term_budget / 2);
+    bool open = false;
+    for (int64_t b = t->level_begin[L0]; b < t->level_begin[L0 + 1]; ++b) {
+      if (sub_mem[b] == 0 && t->b_kind[b] != KIND_INNER) continue;
+      if (open && used + sub_mem[b] > room) {
+        ++nbatch;
+        used = 0;
+      }
+      batch_of[b] = nbatch;
+      used += sub_mem[b];
+      open = true;
+    }
+    if (open) ++nbatch;
+  }
+  c.st.n_batches = nbatch + 1;
 
   // output matrix
   HMat* C = new HMat();
   C->tree = t;
   tree_retain(t);
-  const int64_t nb = int64_t(t->b_tau.size());
   C->rank.assign(nb, 0);
   C->off.assign(nb, -1);
-  std::vector<int32_t> far, near;
-  for (int32_t b : t->leaves) (t->b_kind[b] == KIND_F ? far : near).push_back(b);
-  c.st.n_far = int64_t(far.size());
-  c.st.n_near = int64_t(near.size());
+  std::vector<int32_t> far_all, near_all;
+  for (int32_t b : t->leaves) (t->b_kind[b] == KIND_F ? far_all : near_all).push_back(b);
+  c.st.n_far = int64_t(far_all.size());
+  c.st.n_near = int64_t(near_all.size());
   int64_t near_len = 0;
   std::vector<int64_t> near_off(nb, -1);
-  for (int32_t b : near) {
+  for (int32_t b : near_all) {
     near_off[b] = near_len;
     near_len += int64_t(c.m_of(b)) * c.n_of(b);
   }
   DevBuf<double> near_buf(size_t(std::max<int64_t>(near_len, 1)));
-
   const int64_t budget = opts.o.workspace_limit > 0 ? opts.o.workspace_limit : (int64_t(3) << 30);
   const int cap_est = std::min(64, opts.o.b0 + opts.o.max_growth * opts.o.probes);
-  // nearfield evaluation
-  double tn = now_seconds();
-  for (size_t i = 0; i < near.size();) {
-    Chunk ch;
-    int64_t used = 0;
-    while (i < near.size()) {
-      int64_t cst = target_cost(c, near[i], false, opts, cap_est);
-      if (!ch.blocks.empty() && used + cst > budget) break;
-      used += cst;
-      ch.blocks.push_back(near[i++]);
-    }
-    build_chunk(c, ch);
-    upload_chunk(ch, s);
-    std::vector<int64_t> coff;
-    for (int32_t b : ch.blocks) coff.push_back(near_off[b]);
-    evaluate_chunk(c, ch, near_buf.p, coff);
-  }
-  c.st.t_near = now_seconds() - tn;
-
-  // farfield compression
   std::vector<FarOut> outs;
-  for (size_t i = 0; i < far.size();) {
-    Chunk ch;
-    int64_t used = 0;
-    while (i < far.size()) {
-      int64_t cst = target_cost(c, far[i], true, opts, cap_est);
-      if (!ch.blocks.empty() && used + cst > budget) break;
-      used += cst;
-      ch.blocks.push_back(far[i++]);
+
+  auto process_targets = [&](const std::vector<int32_t>& near, const std::vector<int32_t>& far) {
+    double tn = now_seconds();
+    for (size_t i = 0; i < near.size();) {
+      Chunk ch;
+      int64_t used = 0;
+      while (i < near.size()) {
+        int64_t cst = target_cost(c, near[i], false, opts, cap_est);
+        if (!ch.blocks.empty() && used + cst > budget) break;
+        used += cst;
+        ch.blocks.push_back(near[i++]);
+      }
+      build_chunk(c, ch);
+      upload_chunk(ch, s);
+      std::vector<int64_t> coff;
+      for (int32_t b : ch.blocks) coff.push_back(near_off[b]);
+      evaluate_chunk(c, ch, near_buf.p, coff);
     }
-    build_chunk(c, ch);
-    upload_chunk(ch, s);
-    std::vector<int32_t> w0(ch.blocks.size(), opts.o.b0);
-    outs.emplace_back();
-    compress_chunk(c, ch, w0, outs.back());
+    c.st.t_near += now_seconds() - tn;
+    for (size_t i = 0; i < far.size();) {
+      Chunk ch;
+      int64_t used = 0;
+      while (i < far.size()) {
+        int64_t cst = target_cost(c, far[i], true, opts, cap_est);
+        if (!ch.blocks.empty() && used + cst > budget) break;
+        used += cst;
+        ch.blocks.push_back(far[i++]);
+      }
+      build_chunk(c, ch);
+      upload_chunk(ch, s);
+      std::vector<int32_t> w0(ch.blocks.size(), opts.o.b0);
+      outs.emplace_back();
+      compress_chunk(c, ch, w0, outs.back());
+    }
+  };
+
+  // global terms and targets (levels <= L0)
+  std::vector<int32_t> gterms;
+  for (int64_t i = 0; i < nsym; ++i)
+    if (t->b_level[c.sym[i].child] <= L0) gterms.push_back(int32_t(i));
+  DevBuf<double> global_pool;
+  {
+    double tc = now_seconds();
+    create_terms(c, gterms, global_pool);
+    c.terms.upload(c.hterms, s);
+    c.tv.terms = c.terms.p;
+    c.st.t_restrict += now_seconds() - tc;
+  }
+  {
+    std::vector<int32_t> nf, ff;
+    for (int32_t b : near_all)
+      if (t->b_level[b] <= L0) nf.push_back(b);
+    for (int32_t b : far_all)
+      if (t->b_level[b] <= L0) ff.push_back(b);
+    process_targets(nf, ff);
+  }
+  // batches of deeper subtrees
+  if (L0 < depth) {
+    std::vector<std::vector<int32_t>> bterms(nbatch), bnear(nbatch), bfar(nbatch);
+    for (int64_t i = 0; i < nsym; ++i) {
+      int32_t ch = c.sym[i].child;
+      if (t->b_level[ch] > L0) bterms[batch_of[root0[ch]]].push_back(int32_t(i));
+    }
+    for (int32_t b : near_all)
+      if (t->b_level[b] > L0) bnear[batch_of[root0[b]]].push_back(b);
+    for (int32_t b : far_all)
+      if (t->b_level[b] > L0) bfar[batch_of[root0[b]]].push_back(b);
+    for (int k = 0; k < nbatch; ++k) {
+      DevBuf<double> batch_pool;
+      double tc = now_seconds();
+      create_terms(c, bterms[k], batch_pool);
+      c.terms.upload(c.hterms, s);
+      c.tv.terms = c.terms.p;
+      c.st.t_restrict += now_seconds() - tc;
+      process_targets(bnear[k], bfar[k]);
+    }
   }
 
   // assemble C's pool: nearfield blocks, then farfield chunks
@@ -894,7 +990,7 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   C->pool.alloc(size_t(std::max<int64_t>(total, 1)));
   if (near_len)
     HM_CHECK_HIP(hipMemcpyAsync(C->pool.p, near_buf.p, 8 * near_len, hipMemcpyDeviceToDevice, s));
-  for (int32_t b : near) C->off[b] = near_off[b];
+  for (int32_t b : near_all) C->off[b] = near_off[b];
   for (size_t k = 0; k < outs.size(); ++k) {
     auto& o = outs[k];
     if (o.len) HM_CHECK_HIP(hipMemcpyAsync(C->pool.p + base[k], o.buf.p, 8 * o.len, hipMemcpyDeviceToDevice, s));
