@@ -151,7 +151,24 @@ typedef struct {
   int64_t peak_bytes;        /* peak device workspace of the call */
   int32_t n_batches;         /* subtree batches the product was split into */
   int32_t rank_hist[65];     /* output ranks; index 64 counts ranks >= 64 */
+  /* Per kernel family (HMAT_KERN_*): launches, summed launch durations measured
+   * with HIP events on the product's stream (only with opts.time_kernels), and
+   * the algorithmic operand bytes and flops those launches processed. */
+  int64_t kern_launches[8];
+  double kern_time[8];
+  double kern_bytes[8];
+  double kern_flops[8];
 } hmat_stats;
+
+/* Kernel families of hmat_stats.kern_* */
+enum {
+  HMAT_KERN_TERM_REDUCE = 0,   /* core (R^T X) per (target, low-rank term) */
+  HMAT_KERN_LEAF_REDUCE = 1,   /* R^T X per (subtree product, low-rank leaf) */
+  HMAT_KERN_SUBTREE_EXPAND = 2,/* subtree products: L T and D X per output leaf cluster */
+  HMAT_KERN_GATHER = 3,        /* per target: sum of L V over its terms and pair results */
+  HMAT_KERN_COMPRESS = 4,      /* orthogonalisation, probe residual, core SVD, output */
+  HMAT_KERN_FUSED_TERMS = 5    /* fused term reduce + expand for small targets */
+};
 
 typedef struct {
   int32_t precision;   /* HMAT_FP64 (default), HMAT_FP32_APPLY, HMAT_BF16_SKETCH */
@@ -161,7 +178,7 @@ typedef struct {
   int32_t probes;      /* probe columns of the a-posteriori check (default 8) */
   int32_t max_growth;  /* growth rounds before HMAT_ERR_NOT_CONVERGED (default 6) */
   int32_t p_l;         /* oversampling added to a predicted rank (default 3) */
-  int32_t reserved;
+  int32_t time_kernels;/* 1: time every kernel launch with HIP events into stats */
   double delta;        /* residual target: E <= delta * eps * ||S||_F (default 0.2) */
   uint64_t seed;       /* random stream of the sketches (default 0x5eed) */
   void* stream;        /* hipStream_t (0 = null stream) */

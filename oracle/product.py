@@ -142,3 +142,52 @@ def global_error_estimate(C: HMatrix, A: HMatrix, B: HMatrix, iters: int = 10, s
         Xp, _ = np.linalg.qr(B.rmatvec(A.rmatvec(Yp)))
     est_norm = float(np.linalg.norm(A.matvec(B.matvec(Xp))))
     return est_err, est_norm
+
+
+class LeafStrips:
+    """Strip densification from an arbitrary source of leaves: arrays of the
+    leaves' row/column ranges and a callable returning a leaf's dense block.
+    Used on large H-matrices where only the leaves a strip touches are fetched."""
+
+    def __init__(self, n, r0, r1, c0, c1, get_dense):
+        self.n = n
+        self.r0, self.r1, self.c0, self.c1 = (np.asarray(a, dtype=np.int64) for a in (r0, r1, c0, c1))
+        self.get = get_dense
+        self.cache = {}
+
+    def leaf(self, i):
+        if i not in self.cache:
+            self.cache[i] = self.get(int(i))
+        return self.cache[i]
+
+    def rows_needed(self, a, b):
+        return np.nonzero((self.r0 < b) & (self.r1 > a))[0]
+
+    def cols_needed(self, a, b):
+        return np.nonzero((self.c0 < b) & (self.c1 > a))[0]
+
+    def row_strip(self, a, b):
+        S = np.zeros((b - a, self.n))
+        for i in self.rows_needed(a, b):
+            D = self.leaf(i)
+            lo, hi = max(a, self.r0[i]), min(b, self.r1[i])
+            S[lo - a:hi - a, self.c0[i]:self.c1[i]] = D[lo - self.r0[i]:hi - self.r0[i]]
+        return S
+
+    def col_strip(self, a, b):
+        S = np.zeros((self.n, b - a))
+        for i in self.cols_needed(a, b):
+            D = self.leaf(i)
+            lo, hi = max(a, self.c0[i]), min(b, self.c1[i])
+            S[self.r0[i]:self.r1[i], lo - a:hi - a] = D[:, lo - self.c0[i]:hi - self.c0[i]]
+        return S
+
+
+def oracle_block(sa: LeafStrips, sb: LeafStrips, r0, r1, c0, c1, kind, eps):
+    """The oracle's answer for one leaf of the product: the exact block and, for a
+    farfield leaf, its singular values and epsilon-rank (Eckart-Young)."""
+    D = sa.row_strip(r0, r1) @ sb.col_strip(c0, c1)
+    if kind == KIND_F:
+        s = np.linalg.svd(D, compute_uv=False)
+        return D, s, eps_rank(s, eps)
+    return D, None, None

@@ -95,6 +95,51 @@ void build_kpref(const HMat* M, const DfsInfo& d, DevMat& dm, hipStream_t s) {
   dm.kpref.upload(dm.hkpref, s);
 }
 
+// Algorithmic work of one kernel family for one target in one pass direction:
+// bytes = a + b * w, flops = f * w for a pass of width w.
+struct Coef {
+  double a = 0, b = 0, f = 0;
+};
+enum { K_TERM = 0, K_LEAF = 1, K_EXPAND = 2, K_GATHER = 3, K_COMPRESS = 4 };
+
+// Per matrix, prefix sums over the depth-first leaf order of the quantities the
+// subtree kernels stream (forward f / transposed t).
+struct SubSums {
+  std::vector<double> in_f, in_t, rin_f, rin_t, klr, out_f, out_t, vin_f, vin_t;
+};
+
+// HIP-event timing of kernel launches on the product's stream.
+struct KernTimer {
+  bool on = false;
+  hipStream_t s = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
+  void begin(int kind) {
+    if (!on) return;
+    hipEvent_t a, b;
+    HM_CHECK_HIP(hipEventCreate(&a));
+    HM_CHECK_HIP(hipEventCreate(&b));
+    HM_CHECK_HIP(hipEventRecord(a, s));
+    ev.push_back({kind, {a, b}});
+  }
+  void end() {
+    if (!on) return;
+    HM_CHECK_HIP(hipEventRecord(ev.back().second.second, s));
+  }
+  void resolve(hmat_stats& st) {
+    if (!on) return;
+    HM_CHECK_HIP(hipStreamSynchronize(s));
+    for (auto& e : ev) {
+      float ms = 0.f;
+      HM_CHECK_HIP(hipEventElapsedTime(&ms, e.second.first, e.second.second));
+      st.kern_time[e.first] += 1e-3 * ms;
+      st.kern_launches[e.first] += 1;
+      (void)hipEventDestroy(e.second.first);
+      (void)hipEventDestroy(e.second.second);
+    }
+    ev.clear();
+  }
+};
+
 struct Ctx {
   const Tree* t;
   const HMat* A;
@@ -115,6 +160,9 @@ struct Ctx {
   Opts opts;
   DevBuf<double> omega;  // Gaussian columns shared by all targets, rows keyed by position
   int64_t omega_cols = 0;
+  KernTimer timer;
+  SubSums sa, sb;
+  double alg_flops = 0, alg_bytes = 0;  // minimum algorithmic work (final ranks as widths)
 
   int32_t m_of(int32_t b) const { return t->c_size[t->b_tau[b]]; }
   int32_t n_of(int32_t b) const { return t->c_size[t->b_sigma[b]]; }
@@ -204,6 +252,58 @@ void add_subtree_rows(const Tree& t, int32_t owner, int32_t cluster, std::vector
   }
 }
 
+void build_subsums(const Ctx& c, const HMat* M, SubSums& S) {
+  const Tree& t = *c.t;
+  const size_t nl = c.dfs.dfs_block.size();
+  for (auto* v : {&S.in_f, &S.in_t, &S.rin_f, &S.rin_t, &S.klr, &S.out_f, &S.out_t, &S.vin_f, &S.vin_t})
+    v->assign(nl + 1, 0.0);
+  for (size_t i = 0; i < nl; ++i) {
+    const int32_t b = c.dfs.dfs_block[i];
+    const double m = t.c_size[t.b_tau[b]], n = t.c_size[t.b_sigma[b]];
+    const double lct = t.c_lc_end[t.b_tau[b]] - t.c_lc_begin[t.b_tau[b]];
+    const double lcs = t.c_lc_end[t.b_sigma[b]] - t.c_lc_begin[t.b_sigma[b]];
+    double in_f = 0, in_t = 0, rin_f = 0, rin_t = 0, klr = 0, out_f, out_t, vin_f, vin_t;
+    if (t.b_kind[b] == KIND_F) {
+      const double k = M->rank[b];
+      in_f = n * k, in_t = m * k, rin_f = k > 0 ? n : 0, rin_t = k > 0 ? m : 0, klr = k;
+      out_f = m * k, out_t = n * k, vin_f = k * lct, vin_t = k * lcs;
+    } else {
+      out_f = out_t = m * n, vin_f = n * lct, vin_t = m * lcs;
+    }
+    S.in_f[i + 1] = S.in_f[i] + in_f;
+    S.in_t[i + 1] = S.in_t[i] + in_t;
+    S.rin_f[i + 1] = S.rin_f[i] + rin_f;
+    S.rin_t[i + 1] = S.rin_t[i] + rin_t;
+    S.klr[i + 1] = S.klr[i] + klr;
+    S.out_f[i + 1] = S.out_f[i] + out_f;
+    S.out_t[i + 1] = S.out_t[i] + out_t;
+    S.vin_f[i + 1] = S.vin_f[i] + vin_f;
+    S.vin_t[i + 1] = S.vin_t[i] + vin_t;
+  }
+}
+
+// Work of a subtree product of width w on block q of matrix mat (trans: M^T X):
+// leaf reductions and output expansion.
+void subtree_coef(const Ctx& c, int mat, int32_t q, int trans, Coef& leaf, Coef& expand) {
+  const SubSums& S = mat ? c.sb : c.sa;
+  const int32_t lo = c.dfs.lo[q], hi = c.dfs.hi[q];
+  auto d = [&](const std::vector<double>& v) { return v[hi] - v[lo]; };
+  const double in = trans ? d(S.in_t) : d(S.in_f), rin = trans ? d(S.rin_t) : d(S.rin_f);
+  const double out = trans ? d(S.out_t) : d(S.out_f), vin = trans ? d(S.vin_t) : d(S.vin_f);
+  const double mout = c.t->c_size[trans ? c.t->b_sigma[q] : c.t->b_tau[q]];
+  leaf.a += 8 * in;
+  leaf.b += 8 * (rin + d(S.klr));
+  leaf.f += 2 * in;
+  expand.a += 8 * out;
+  expand.b += 8 * (vin + mout);
+  expand.f += 2 * out;
+}
+
+void account(hmat_stats& st, int kind, const Coef& k, double w) {
+  st.kern_bytes[kind] += k.a + k.b * w;
+  st.kern_flops[kind] += k.f * w;
+}
+
 // leaf items of a subtree task; returns the workspace (doubles) its leaf products need
 int64_t add_subtree_leaves(const Ctx& c, int32_t owner, int mat, int32_t q, std::vector<LeafItem>& items) {
   const Tree& t = *c.t;
@@ -250,6 +350,13 @@ void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& poo
         tk.tws = st.data_off + int64_t(j0) * st.kl;
         ff.leaf_items.push_back(LeafItem{int32_t(ff.tasks.size()), st.a_blk});
         ff.tasks.push_back(tk);
+        {
+          const double nr = t.c_size[rho], w = tk.w;
+          Coef k{8 * nr * st.kl, 8 * (nr + st.kl), 2 * nr * st.kl};
+          account(c.st, K_LEAF, k, w);
+          c.alg_bytes += k.a + k.b * w;
+          c.alg_flops += k.f * w;
+        }
       }
     } else if (st.type == T_FH || st.type == T_HF) {
       const bool isfh = st.type == T_FH;
@@ -276,6 +383,14 @@ void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& poo
         fh.ws_len += add_subtree_leaves(c, owner, tk.mat, tk.q, fh.leaf_items);
         add_subtree_rows(t, owner, isfh ? t.b_sigma[tk.q] : t.b_tau[tk.q], fh.row_items);
         fh.tasks.push_back(tk);
+        {
+          Coef kl, ke;
+          subtree_coef(c, tk.mat, tk.q, tk.trans, kl, ke);
+          account(c.st, K_LEAF, kl, tk.w);
+          account(c.st, K_EXPAND, ke, tk.w);
+          c.alg_bytes += kl.a + kl.b * tk.w + ke.a + ke.b * tk.w;
+          c.alg_flops += (kl.f + ke.f) * tk.w;
+        }
       }
     }
   }
@@ -284,7 +399,9 @@ void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& poo
     dt.upload(ff.tasks, s);
     DevBuf<LeafItem> dl;
     dl.upload(ff.leaf_items, s);
+    c.timer.begin(K_LEAF);
     launch_leaf_p1(dl.p, ff.leaf_items.size(), dt.p, nullptr, c.tv, c.ma, c.mb, P, s);
+    c.timer.end();
     HM_CHECK_HIP(hipStreamSynchronize(s));
   }
   if (!fh.tasks.empty()) {
@@ -295,8 +412,12 @@ void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& poo
     DevBuf<RowItem> dr;
     dr.upload(fh.row_items, s);
     DevBuf<double> ws(size_t(std::max<int64_t>(fh.ws_len, 1)));
+    c.timer.begin(K_LEAF);
     launch_leaf_p1(dl.p, fh.leaf_items.size(), dt.p, nullptr, c.tv, c.ma, c.mb, ws.p, s);
+    c.timer.end();
+    c.timer.begin(K_EXPAND);
     launch_subtree_p2(dr.p, fh.row_items.size(), dt.p, nullptr, c.tv, c.ma, c.mb, ws.p, s);
+    c.timer.end();
     HM_CHECK_HIP(hipStreamSynchronize(s));
   }
   // device descriptors of these terms
@@ -373,6 +494,7 @@ struct Chunk {
   DevBuf<TermItem> d_terms;
   DevBuf<double> vbuf, wsf, wst, pairbuf;
   DevBuf<TDesc> d_td;
+  std::vector<Coef> coef[4][2];  // per kernel family and direction, per target
 };
 
 int64_t target_cost(const Ctx& c, int32_t b, bool far, const Opts& o, int cap) {
@@ -398,16 +520,45 @@ void build_chunk(const Ctx& c, Chunk& ch) {
   const Tree& t = *c.t;
   const int nt = int(ch.blocks.size());
   ch.info.resize(nt);
+  for (int k = 0; k < 4; ++k)
+    for (int d = 0; d < 2; ++d) ch.coef[k][d].assign(nt, Coef{});
   for (int i = 0; i < nt; ++i) {
     const int32_t b = ch.blocks[i];
     TInfo& ti = ch.info[i];
     ti.block = b;
     ti.vbase = ch.vlen;
+    const double mt = t.c_size[t.b_tau[b]], nt_ = t.c_size[t.b_sigma[b]];
+    double skl = 0, skr = 0;
     for (int32_t a = b; a >= 0; a = t.b_parent[a])
       for (int32_t j = c.group_ptr_h[a]; j < c.group_ptr_h[a + 1]; ++j) {
         ch.term_items.push_back(TermItem{i, j, ch.vlen});
         ch.vlen += int64_t(std::max(c.sym[j].kl, c.sym[j].kr)) * PW;
+        const SymTerm& sy = c.sym[j];
+        const double core = sy.type == T_FF ? double(sy.kl) * sy.kr : 0.0;
+        Coef& f = ch.coef[K_TERM][0][i];
+        f.a += 8 * (nt_ * sy.kr + core);
+        f.b += 8 * (nt_ + sy.kl);
+        f.f += 2 * (nt_ * sy.kr + core);
+        Coef& tr = ch.coef[K_TERM][1][i];
+        tr.a += 8 * (mt * sy.kl + core);
+        tr.b += 8 * (mt + sy.kr);
+        tr.f += 2 * (mt * sy.kl + core);
+        skl += sy.kl;
+        skr += sy.kr;
       }
+    {
+      const int32_t np = c.hptr[b + 1] - c.hptr[b];
+      const double nchf = t.c_lc_end[t.b_tau[b]] - t.c_lc_begin[t.b_tau[b]];
+      const double ncht = t.c_lc_end[t.b_sigma[b]] - t.c_lc_begin[t.b_sigma[b]];
+      Coef& gf = ch.coef[K_GATHER][0][i];
+      gf.a = 8 * mt * skl;
+      gf.b = 8 * (skl * nchf + mt * (np + 1));
+      gf.f = 2 * mt * skl + mt * np;
+      Coef& gt = ch.coef[K_GATHER][1][i];
+      gt.a = 8 * nt_ * skr;
+      gt.b = 8 * (skr * ncht + nt_ * (np + 1));
+      gt.f = 2 * nt_ * skr + nt_ * np;
+    }
     ti.hp_begin = int32_t(ch.pairs.size());
     const int32_t tau = t.b_tau[b], sig = t.b_sigma[b];
     const int32_t m = t.c_size[tau], n = t.c_size[sig];
@@ -415,6 +566,10 @@ void build_chunk(const Ctx& c, Chunk& ch) {
       const int32_t rho = c.hrho[j];
       const int32_t qa = t.find_block(tau, rho), qb = t.find_block(rho, sig);
       if (qa < 0 || qb < 0) throw Error(HMAT_ERR_INTERNAL, "pair blocks missing");
+      subtree_coef(c, 1, qb, 0, ch.coef[K_LEAF][0][i], ch.coef[K_EXPAND][0][i]);
+      subtree_coef(c, 0, qa, 0, ch.coef[K_LEAF][0][i], ch.coef[K_EXPAND][0][i]);
+      subtree_coef(c, 0, qa, 1, ch.coef[K_LEAF][1][i], ch.coef[K_EXPAND][1][i]);
+      subtree_coef(c, 1, qb, 1, ch.coef[K_LEAF][1][i], ch.coef[K_EXPAND][1][i]);
       const int64_t off1 = ch.pair_len;
       ch.pair_len += int64_t(t.c_size[rho]) * PW;
       const int64_t off2 = ch.pair_len;
@@ -523,20 +678,45 @@ void run_pass(Ctx& c, Chunk& ch, const std::vector<TDesc>& td, bool trans) {
   hipStream_t s = c.s;
   ch.d_td.upload(td, s);  // synchronous: td is rewritten for the next pass
   const TDesc* dtd = ch.d_td.p;
+  const int d = trans ? 1 : 0;
+  for (size_t i = 0; i < td.size(); ++i)
+    if (td[i].w)
+      for (int k = 0; k < 4; ++k) account(c.st, k, ch.coef[k][d][i], td[i].w);
+  auto& tasks = trans ? ch.d_tasks_t : ch.d_tasks_f;
+  auto& ws = trans ? ch.wst : ch.wsf;
+  auto& l1 = trans ? ch.d_l1t : ch.d_l1f;
+  auto& l2 = trans ? ch.d_l2t : ch.d_l2f;
+  auto& r1 = trans ? ch.d_r1t : ch.d_r1f;
+  auto& r2 = trans ? ch.d_r2t : ch.d_r2f;
+  const size_t nl1 = trans ? ch.l1t.size() : ch.l1f.size(), nl2 = trans ? ch.l2t.size() : ch.l2f.size();
+  const size_t nr1 = trans ? ch.r1t.size() : ch.r1f.size(), nr2 = trans ? ch.r2t.size() : ch.r2f.size();
+  c.timer.begin(K_TERM);
   launch_term_p1(ch.d_terms.p, ch.term_items.size(), dtd, ch.d_info.p, c.tv, ch.vbuf.p, s);
-  if (!trans) {
-    launch_leaf_p1(ch.d_l1f.p, ch.l1f.size(), ch.d_tasks_f.p, dtd, c.tv, c.ma, c.mb, ch.wsf.p, s);
-    launch_subtree_p2(ch.d_r1f.p, ch.r1f.size(), ch.d_tasks_f.p, dtd, c.tv, c.ma, c.mb, ch.wsf.p, s);
-    launch_leaf_p1(ch.d_l2f.p, ch.l2f.size(), ch.d_tasks_f.p, dtd, c.tv, c.ma, c.mb, ch.wsf.p, s);
-    launch_subtree_p2(ch.d_r2f.p, ch.r2f.size(), ch.d_tasks_f.p, dtd, c.tv, c.ma, c.mb, ch.wsf.p, s);
-    launch_gather(ch.d_gf.p, ch.gf.size(), dtd, ch.d_info.p, ch.d_pairs.p, c.tv, ch.vbuf.p, s);
-  } else {
-    launch_leaf_p1(ch.d_l1t.p, ch.l1t.size(), ch.d_tasks_t.p, dtd, c.tv, c.ma, c.mb, ch.wst.p, s);
-    launch_subtree_p2(ch.d_r1t.p, ch.r1t.size(), ch.d_tasks_t.p, dtd, c.tv, c.ma, c.mb, ch.wst.p, s);
-    launch_leaf_p1(ch.d_l2t.p, ch.l2t.size(), ch.d_tasks_t.p, dtd, c.tv, c.ma, c.mb, ch.wst.p, s);
-    launch_subtree_p2(ch.d_r2t.p, ch.r2t.size(), ch.d_tasks_t.p, dtd, c.tv, c.ma, c.mb, ch.wst.p, s);
-    launch_gather(ch.d_gt.p, ch.gt.size(), dtd, ch.d_info.p, ch.d_pairs.p, c.tv, ch.vbuf.p, s);
+  c.timer.end();
+  if (nl1) {
+    c.timer.begin(K_LEAF);
+    launch_leaf_p1(l1.p, nl1, tasks.p, dtd, c.tv, c.ma, c.mb, ws.p, s);
+    c.timer.end();
   }
+  if (nr1) {
+    c.timer.begin(K_EXPAND);
+    launch_subtree_p2(r1.p, nr1, tasks.p, dtd, c.tv, c.ma, c.mb, ws.p, s);
+    c.timer.end();
+  }
+  if (nl2) {
+    c.timer.begin(K_LEAF);
+    launch_leaf_p1(l2.p, nl2, tasks.p, dtd, c.tv, c.ma, c.mb, ws.p, s);
+    c.timer.end();
+  }
+  if (nr2) {
+    c.timer.begin(K_EXPAND);
+    launch_subtree_p2(r2.p, nr2, tasks.p, dtd, c.tv, c.ma, c.mb, ws.p, s);
+    c.timer.end();
+  }
+  c.timer.begin(K_GATHER);
+  launch_gather(trans ? ch.d_gt.p : ch.d_gf.p, trans ? ch.gt.size() : ch.gf.size(), dtd, ch.d_info.p,
+                ch.d_pairs.p, c.tv, ch.vbuf.p, s);
+  c.timer.end();
 }
 
 struct FarOut {
@@ -673,9 +853,13 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
   {
     int maxw0 = 0;
     for (auto& T : h) maxw0 = std::max(maxw0, T.w0);
-    launch_orth_append(dt.p, nt, 0, maxw0, cp, s);  // each target uses its own w0 columns
+    c.timer.begin(K_COMPRESS);
+    launch_orth_append(dt.p, nt, 0, maxw0, cp, s);
+    c.timer.end();  // each target uses its own w0 columns
   }
-  launch_probe_residual(dt.p, nt, cp, s);
+  c.timer.begin(K_COMPRESS);
+    launch_probe_residual(dt.p, nt, cp, s);
+    c.timer.end();
   fetch();
   double t1 = now_seconds();
   c.st.t_sketch += t1 - t0;
@@ -705,7 +889,9 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
     dt.upload(h, s);
     std::vector<int> r_old(nt);
     for (int i = 0; i < nt; ++i) r_old[i] = h[i].r;
+    c.timer.begin(K_COMPRESS);
     launch_orth_append(dt.p, nt, cap, g, cp, s);
+    c.timer.end();
     fetch();
     std::vector<int> act(nt);
     for (int i = 0; i < nt; ++i) {
@@ -726,12 +912,16 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
     project(r_old, rto);
     for (int i = 0; i < nt; ++i) h[i].rz = h[i].r;
     dt.upload(h, s);
+    c.timer.begin(K_COMPRESS);
     launch_probe_residual(dt.p, nt, cp, s);
+    c.timer.end();
     c.st.t_project += now_seconds() - tb;
   }
   double t3 = now_seconds();
   launch_check(dt.p, nt, cp, pending.p, s);
-  launch_core(dt.p, nt, cp, s);
+  c.timer.begin(K_COMPRESS);
+    launch_core(dt.p, nt, cp, s);
+    c.timer.end();
   fetch();
   out.blocks.clear();
   out.ranks.clear();
@@ -746,10 +936,23 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
     T.out_off = out.len;
     out.len += int64_t(T.k) * (T.m + T.n);
     c.st.rank_hist[std::min(T.k, 64)]++;
+    // minimum algorithmic work of this target: one forward and one transposed pass of
+    // width k, the core factorisations and the factor output
+    const double w = std::max(T.k, 1);
+    for (int k = 0; k < 4; ++k)
+      for (int d = 0; d < 2; ++d) {
+        const Coef& cf = ch.coef[k][d][i];
+        c.alg_bytes += cf.a + cf.b * w;
+        c.alg_flops += cf.f * w;
+      }
+    c.alg_flops += 4.0 * (T.m + T.n) * w * w + 22.0 * w * w * w;
+    c.alg_bytes += 8.0 * (T.m + T.n) * T.k;
   }
   out.buf.alloc(size_t(std::max<int64_t>(out.len, 1)));
   dt.upload(h, s);
-  launch_write_factors(dt.p, nt, cp, out.buf.p, s);
+  c.timer.begin(K_COMPRESS);
+    launch_write_factors(dt.p, nt, cp, out.buf.p, s);
+    c.timer.end();
   HM_CHECK_HIP(hipStreamSynchronize(s));
   c.st.t_core += now_seconds() - t3;
 }
@@ -778,6 +981,14 @@ void evaluate_chunk(Ctx& c, Chunk& ch, double* cpool, const std::vector<int64_t>
       d.split = d.w;
     }
     run_pass(c, ch, td, false);
+  }
+  for (int i = 0; i < nt; ++i) {
+    const double w = c.n_of(ch.blocks[i]);
+    for (int k = 0; k < 4; ++k) {
+      const Coef& cf = ch.coef[k][0][i];
+      c.alg_bytes += cf.a + cf.b * w;
+      c.alg_flops += cf.f * w;
+    }
   }
   HM_CHECK_HIP(hipStreamSynchronize(c.s));
   (void)t;
@@ -809,6 +1020,10 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   build_kpref(B, c.dfs, c.db, s);
   c.ma = c.da.view(A);
   c.mb = c.db.view(B);
+  build_subsums(c, A, c.sa);
+  build_subsums(c, B, c.sb);
+  c.timer.on = opts.o.time_kernels != 0;
+  c.timer.s = s;
   symbolic(c);
   c.b_parent.upload(t->b_parent, s);
   c.b_dfs.upload(c.dfs.dfs_of_block, s);
@@ -1001,6 +1216,9 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   }
   C->upload_meta(s);
   HM_CHECK_HIP(hipStreamSynchronize(s));
+  c.timer.resolve(c.st);
+  c.st.flops_alg = c.alg_flops;
+  c.st.bytes_alg = c.alg_bytes;
   c.st.t_total = now_seconds() - t_start;
   if (opts.o.stats) *opts.o.stats = c.st;
   *Cout = C;

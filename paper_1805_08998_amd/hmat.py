@@ -17,6 +17,8 @@ HMAT_OK, HMAT_ERR_ARG, HMAT_ERR_TREE_MISMATCH, HMAT_ERR_NOT_CONVERGED = 0, 1, 2,
 HMAT_ERR_DEVICE, HMAT_ERR_OOM, HMAT_ERR_INTERNAL = 4, 5, 6
 HMAT_FP64, HMAT_FP32_APPLY, HMAT_BF16_SKETCH = 0, 1, 2
 HMAT_RANK_ADAPTIVE, HMAT_RANK_PREDICT = 0, 1
+KERN_NAMES = ["term_reduce", "leaf_reduce", "subtree_expand", "gather", "compress", "fused_terms", "k6", "k7"]
+KERN_SYMBOLS = ["k_term_p1", "k_leaf_p1", "k_subtree_p2", "k_gather", "compress", "k_fused_terms", "", ""]
 KERNELS = {"laplace_4pi": 0, "inv_dist": 1, "exp": 2}
 
 
@@ -39,17 +41,21 @@ class hmat_stats(C.Structure):
                 ("bytes_alg", C.c_double), ("n_far", C.c_int64), ("n_near", C.c_int64),
                 ("n_growth_rounds", C.c_int64), ("n_grown_blocks", C.c_int64),
                 ("n_not_converged", C.c_int64), ("n_fallback", C.c_int64), ("sketch_columns", C.c_int64),
-                ("peak_bytes", C.c_int64), ("n_batches", C.c_int32), ("rank_hist", C.c_int32 * 65)]
+                ("peak_bytes", C.c_int64), ("n_batches", C.c_int32), ("rank_hist", C.c_int32 * 65),
+                ("kern_launches", C.c_int64 * 8), ("kern_time", C.c_double * 8), ("kern_bytes", C.c_double * 8),
+                ("kern_flops", C.c_double * 8)]
 
     def as_dict(self):
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "rank_hist"}
-        d["rank_hist"] = list(self.rank_hist)
+        d = {}
+        for f, _ in self._fields_:
+            v = getattr(self, f)
+            d[f] = list(v) if hasattr(v, "__len__") else v
         return d
 
 
 class hmat_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("rank_mode", C.c_int32), ("b0", C.c_int32), ("growth", C.c_int32),
-                ("probes", C.c_int32), ("max_growth", C.c_int32), ("p_l", C.c_int32), ("reserved", C.c_int32),
+                ("probes", C.c_int32), ("max_growth", C.c_int32), ("p_l", C.c_int32), ("time_kernels", C.c_int32),
                 ("delta", C.c_double), ("seed", C.c_uint64), ("stream", C.c_void_p),
                 ("rank_model", C.c_void_p), ("stats", C.POINTER(hmat_stats)),
                 ("workspace_limit", C.c_int64)]

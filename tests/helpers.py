@@ -58,45 +58,25 @@ def oracle_to_blocks(Hm: HMatrix):
     return np.array(ranks, dtype=np.int32), np.array(offs, dtype=np.int64), pool
 
 
-class PartialExport:
-    """Leaves of a library H-matrix fetched on demand (hmat_block_get), indexed
-    for strip densification by the oracle at sizes where a full export is too big."""
+def leaf_source(H, tree, M):
+    """LeafStrips over a library H-matrix, fetching leaves with hmat_block_get."""
+    from oracle.product import LeafStrips
+    cl = H.hmat_tree_clusters(tree)
+    bl = H.hmat_tree_blocks(tree)
+    n = H.hmat_tree_info(tree)["n"]
+    leaf_ids = np.nonzero(bl["kind"] != 0)[0]
+    t, s = bl["tau"][leaf_ids], bl["sigma"][leaf_ids]
+    r0 = cl["begin"][t].astype(np.int64)
+    c0 = cl["begin"][s].astype(np.int64)
 
-    def __init__(self, H, tree, M):
-        self.H, self.M = H, M
-        cl = H.hmat_tree_clusters(tree)
-        bl = H.hmat_tree_blocks(tree)
-        self.n = H.hmat_tree_info(tree)["n"]
-        leaf_ids = np.nonzero(bl["kind"] != 0)[0]
-        self.kind = bl["kind"][leaf_ids]
-        t, s = bl["tau"][leaf_ids], bl["sigma"][leaf_ids]
-        self.r0 = cl["begin"][t].astype(np.int64)
-        self.r1 = self.r0 + cl["size"][t]
-        self.c0 = cl["begin"][s].astype(np.int64)
-        self.c1 = self.c0 + cl["size"][s]
-        self.cache = {}
+    def get(i):
+        d, U, V = H.hmat_block_get(M, i)
+        return (U @ V.T) if d["kind"] == 1 else V
 
-    def leaf(self, i):
-        if i not in self.cache:
-            d, U, V = self.H.hmat_block_get(self.M, int(i))
-            self.cache[i] = (U @ V.T) if d["kind"] == 1 else V
-        return self.cache[i]
-
-    def row_strip(self, a, b):
-        S = np.zeros((b - a, self.n))
-        for i in np.nonzero((self.r0 < b) & (self.r1 > a))[0]:
-            D = self.leaf(i)
-            lo, hi = max(a, self.r0[i]), min(b, self.r1[i])
-            S[lo - a:hi - a, self.c0[i]:self.c1[i]] = D[lo - self.r0[i]:hi - self.r0[i]]
-        return S
-
-    def col_strip(self, a, b):
-        S = np.zeros((self.n, b - a))
-        for i in np.nonzero((self.c0 < b) & (self.c1 > a))[0]:
-            D = self.leaf(i)
-            lo, hi = max(a, self.c0[i]), min(b, self.c1[i])
-            S[self.r0[i]:self.r1[i], lo - a:hi - a] = D[:, lo - self.c0[i]:hi - self.c0[i]]
-        return S
+    src = LeafStrips(n, r0, r0 + cl["size"][t], c0, c0 + cl["size"][s], get)
+    src.kind = bl["kind"][leaf_ids]
+    src.level = bl["level"][leaf_ids]
+    return src
 
 
 def sampled_check(H, tree, A, B, C, eps, per_level=3, seed=0, max_rows=2048, log=print):
@@ -104,15 +84,12 @@ def sampled_check(H, tree, A, B, C, eps, per_level=3, seed=0, max_rows=2048, log
     blocks A_H[tau, :] B_H[:, sigma] built from strips. Returns the list of
     (level, kind, rows, cols, err, rank, kstar, ok)."""
     from oracle.product import check_block
-    pa, pb, pc = PartialExport(H, tree, A), PartialExport(H, tree, B), PartialExport(H, tree, C)
-    bl = H.hmat_tree_blocks(tree)
-    leaf_ids = np.nonzero(bl["kind"] != 0)[0]
-    lev = bl["level"][leaf_ids]
+    pa, pb, pc = leaf_source(H, tree, A), leaf_source(H, tree, B), leaf_source(H, tree, C)
     rng = np.random.default_rng(seed)
     out = []
-    for L in np.unique(lev):
+    for L in np.unique(pc.level):
         for kind in (1, 2):
-            cand = np.nonzero((lev == L) & (pc.kind == kind) & (pc.r1 - pc.r0 <= max_rows))[0]
+            cand = np.nonzero((pc.level == L) & (pc.kind == kind) & (pc.r1 - pc.r0 <= max_rows))[0]
             if cand.size == 0:
                 continue
             for i in rng.choice(cand, min(per_level, cand.size), replace=False):
