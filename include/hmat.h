@@ -158,6 +158,11 @@ typedef struct {
   double kern_time[8];
   double kern_bytes[8];
   double kern_flops[8];
+  /* Time split: [0] symbolic plan, [1] term-creation lists, [2] chunk
+   * partition + upload + waiting for the chunk builder, [3] waiting on the device
+   * inside the compression loop, [4] term-pool allocation, [5] creation-list
+   * upload, [6] creation kernels incl. synchronisation, [7] term publication. */
+  double t_host[8];
 } hmat_stats;
 
 /* Kernel families of hmat_stats.kern_* */

@@ -1,10 +1,13 @@
 // C ABI entry points: handles, error reporting, allocator hook, tree queries,
 // assembly, import/export. Every entry point catches everything and reports
 // through hmat_last_error().
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <unordered_map>
 
 #include "hmat_internal.h"
 
@@ -24,29 +27,144 @@ static void* (*g_alloc)(size_t, void*) = nullptr;
 static void (*g_free)(void*, void*) = nullptr;
 static void* g_ctx = nullptr;
 
+// Caching of device blocks when no allocator hook is set: a freed block keeps
+// its (rounded) size class and an event recorded on the library's current
+// stream; it is handed out again only once that event has completed, so work
+// still queued on the old buffer can never see it reused. On allocation
+// failure the cache is released and the allocation retried.
+static hipStream_t g_stream = 0;
+struct CachedBlock {
+  void* p;
+  hipEvent_t ev;
+};
+static std::map<std::pair<int, size_t>, std::vector<CachedBlock>> g_cache;
+static std::unordered_map<void*, std::pair<int, size_t>> g_live;
+static size_t g_cached_bytes = 0;
+static const size_t kCacheLimit = size_t(64) << 30;
+
+void set_current_stream(hipStream_t s) { g_stream = s; }
+
+static size_t round_size(size_t b) {
+  if (b <= (size_t(1) << 20)) {
+    size_t r = 256;
+    while (r < b) r <<= 1;
+    return r;
+  }
+  const size_t g = size_t(2) << 20;
+  return (b + g - 1) / g * g;
+}
+
+static void release_cache_locked() {
+  for (auto& kv : g_cache)
+    for (auto& cb : kv.second) {
+      (void)hipEventSynchronize(cb.ev);
+      (void)hipEventDestroy(cb.ev);
+      (void)hipFree(cb.p);
+    }
+  g_cache.clear();
+  g_cached_bytes = 0;
+}
+
 void* dev_alloc(size_t bytes) {
   void* p = nullptr;
   if (bytes == 0) bytes = 8;
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
   if (g_alloc) {
     p = g_alloc(bytes, g_ctx);
     if (!p) throw Error(HMAT_ERR_OOM, "allocator hook failed for " + std::to_string(bytes) + " bytes");
     return p;
   }
-  hipError_t e = hipMalloc(&p, bytes);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const size_t rs = round_size(bytes);
+  // best fit: the smallest cached size class of at least rs and at most 1.5 rs
+  for (auto it = g_cache.lower_bound({dev, rs});
+       it != g_cache.end() && it->first.first == dev && it->first.second <= rs + rs / 2; ++it) {
+    auto& v = it->second;
+    for (size_t i = 0; i < v.size(); ++i)
+      if (hipEventQuery(v[i].ev) == hipSuccess) {
+        p = v[i].p;
+        const size_t got = it->first.second;
+        (void)hipEventDestroy(v[i].ev);
+        v.erase(v.begin() + i);
+        g_cached_bytes -= got;
+        g_live[p] = {dev, got};
+        return p;
+      }
+  }
+  hipError_t e = hipMalloc(&p, rs);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    release_cache_locked();
+    e = hipMalloc(&p, rs);
+  }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     throw Error(HMAT_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
   }
+  g_live[p] = {dev, rs};
   return p;
 }
 
 void dev_free(void* p) {
   if (!p) return;
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
   if (g_free) {
     g_free(p, g_ctx);
     return;
   }
-  (void)hipFree(p);
+  auto it = g_live.find(p);
+  if (it == g_live.end()) {
+    (void)hipFree(p);
+    return;
+  }
+  const auto key = it->second;
+  g_live.erase(it);
+  hipEvent_t ev;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev, g_stream) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(p);
+    return;
+  }
+  g_cache[key].push_back({p, ev});
+  g_cached_bytes += key.second;
+  if (g_cached_bytes > kCacheLimit) release_cache_locked();
+}
+
+static std::mutex g_pin_mu;
+static void* g_pin = nullptr;
+static size_t g_pin_size = 0;
+
+void host_to_device(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  const size_t small = size_t(4) << 20;
+  if (bytes <= small) {
+    HM_CHECK_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+    HM_CHECK_HIP(hipStreamSynchronize(s));
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  const size_t chunk = size_t(64) << 20;
+  if (!g_pin) {
+    if (hipHostMalloc(&g_pin, chunk) != hipSuccess) {
+      (void)hipGetLastError();
+      g_pin = nullptr;
+    } else {
+      g_pin_size = chunk;
+    }
+  }
+  if (!g_pin) {  // no pinned memory: plain copy
+    HM_CHECK_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+    HM_CHECK_HIP(hipStreamSynchronize(s));
+    return;
+  }
+  const char* hs = static_cast<const char*>(src);
+  char* dd = static_cast<char*>(dst);
+  for (size_t off = 0; off < bytes; off += g_pin_size) {
+    const size_t len = std::min(g_pin_size, bytes - off);
+    std::memcpy(g_pin, hs + off, len);
+    HM_CHECK_HIP(hipMemcpyAsync(dd + off, g_pin, len, hipMemcpyHostToDevice, s));
+    HM_CHECK_HIP(hipStreamSynchronize(s));
+  }
 }
 
 double now_seconds() {

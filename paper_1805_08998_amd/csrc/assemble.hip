@@ -141,6 +141,7 @@ HMat* assemble_kernel(Tree* t, const hmat_kernel* k, double eps_in, const Opts& 
   HM_REQUIRE(eps_in > 0.0 && eps_in < 1.0, HMAT_ERR_ARG, "eps_in must be in (0, 1)");
   HM_REQUIRE(std::isfinite(k->diag) && std::isfinite(k->shift), HMAT_ERR_ARG, "non-finite diagonal");
   hipStream_t s = opts.stream();
+  set_current_stream(s);
   t->ensure_device(s);
   KernelDev kd{k->kind, k->diag + k->shift};
   const double* xyz = t->dev->xyz_perm.p;

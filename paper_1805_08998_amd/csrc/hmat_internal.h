@@ -38,6 +38,11 @@ void set_last_error(const std::string& msg);
 // ---------------------------------------------------------------- device memory
 void* dev_alloc(size_t bytes);
 void dev_free(void* p);
+// stream on which freed blocks may still be in use (set by every entry point that launches work)
+void set_current_stream(hipStream_t s);
+// Copies host memory to the device and waits; large copies go through a pinned
+// staging buffer (allocated with hipHostMalloc and kept for reuse).
+void host_to_device(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 template <class T>
 struct DevBuf {
@@ -65,10 +70,7 @@ struct DevBuf {
   }
   void upload(const T* h, size_t count, hipStream_t s) {
     if (count > n) alloc(count);
-    if (count) {
-      HM_CHECK_HIP(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, s));
-      HM_CHECK_HIP(hipStreamSynchronize(s));  // the host buffer may change right after
-    }
+    if (count) host_to_device(p, h, count * sizeof(T), s);  // synchronous: h may change right after
   }
   void upload(const std::vector<T>& v, hipStream_t s) { upload(v.data(), v.size(), s); }
 };

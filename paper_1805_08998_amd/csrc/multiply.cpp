@@ -14,6 +14,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <future>
+#include <memory>
 #include <numeric>
 
 #include "compress.h"
@@ -21,14 +23,21 @@
 
 namespace hm {
 
-void launch_leaf_p1(const LeafItem* items, size_t n, const Task* tasks, const TDesc* td, const TreeView& tv,
-                    const MatView& ma, const MatView& mb, double* ws, hipStream_t s);
-void launch_subtree_p2(const RowItem* items, size_t n, const Task* tasks, const TDesc* td, const TreeView& tv,
-                       const MatView& ma, const MatView& mb, const double* ws, hipStream_t s);
-void launch_term_p1(const TermItem* items, size_t n, const TDesc* td, const TInfo* ti, const TreeView& tv,
-                    double* vbuf, hipStream_t s);
-void launch_gather(const RowItem* items, size_t n, const TDesc* td, const TInfo* ti, const HPair* hp,
-                   const TreeView& tv, const double* vbuf, hipStream_t s);
+void launch_leaf_reduce(const int64_t* pre, int ntask, int64_t nitems, const Task* tasks, const TDesc* td,
+                        const int32_t* dfs_block, const TreeView& tv, const MatView& ma, const MatView& mb,
+                        double* ws, hipStream_t s);
+void launch_subtree_expand(const int64_t* pre, int ntask, int64_t nitems, const Task* tasks, const TDesc* td,
+                           const TreeView& tv, const MatView& ma, const MatView& mb, const double* ws,
+                           hipStream_t s);
+void launch_term_reduce(const TermItem* items, size_t n, const TDesc* td, const TInfo* ti, const TreeView& tv,
+                        double* vbuf, hipStream_t s);
+void launch_gather_mfma(const RowItem* items, size_t n, const TDesc* td, const TInfo* ti, const HPair* hp,
+                        const TreeView& tv, const double* vbuf, hipStream_t s);
+void launch_fused_terms(const int32_t* tlist, size_t n, const TDesc* td, const TInfo* ti, const HPair* hp,
+                        const TreeView& tv, hipStream_t s);
+void launch_scatter_terms(const int32_t* ids, const Term* src, Term* dst, int64_t n, hipStream_t s);
+void launch_fused_terms4(const int32_t* tlist, size_t n, const TDesc* td, const TInfo* ti, const HPair* hp,
+                         const TreeView& tv, hipStream_t s);
 
 namespace {
 
@@ -100,7 +109,11 @@ void build_kpref(const HMat* M, const DfsInfo& d, DevMat& dm, hipStream_t s) {
 struct Coef {
   double a = 0, b = 0, f = 0;
 };
-enum { K_TERM = 0, K_LEAF = 1, K_EXPAND = 2, K_GATHER = 3, K_COMPRESS = 4 };
+enum { K_TERM = 0, K_LEAF = 1, K_EXPAND = 2, K_GATHER = 3, K_COMPRESS = 4, K_FUSED = 5 };
+// targets whose clusters both have at most FUSED_MAX (one wave) or FUSED4_MAX (four
+// waves) rows use the fused MFMA kernels
+constexpr int FUSED_MAX = 64;
+constexpr int FUSED4_MAX = 256;
 
 // Per matrix, prefix sums over the depth-first leaf order of the quantities the
 // subtree kernels stream (forward f / transposed t).
@@ -149,11 +162,11 @@ struct Ctx {
   DevMat da, db;
   MatView ma, mb;
   TreeView tv;
-  DevBuf<int32_t> b_parent, b_dfs, group_ptr;
+  DevBuf<int32_t> b_parent, b_dfs, group_ptr, d_dfs_block;
   DevBuf<Term> terms;
   std::vector<SymTerm> sym;
   std::vector<int32_t> group_ptr_h;
-  std::vector<int32_t> hptr, hrho;  // pairs per block
+  std::vector<int32_t> hptr, hrho;  // pairs per block: hptr over blocks, hrho = (rho, A block, B block) triples
   std::vector<Term> hterms;
   hmat_stats st{};
   double eps;
@@ -176,73 +189,107 @@ void symbolic(Ctx& c) {
   const int64_t nb = int64_t(t.b_tau.size());
   c.group_ptr_h.assign(nb + 1, 0);
   c.hptr.assign(nb + 1, 0);
-  std::vector<std::vector<int32_t>> H(nb);  // built per level, released as we go
-  H[0].push_back(0);
-  std::vector<int32_t> gcount(nb, 0), hcount(nb, 0);
-  // pass over blocks in breadth-first order: children of b get their lists now
-  std::vector<std::vector<SymTerm>> per_block_terms(nb);
-  for (int64_t b = 0; b < nb; ++b) {
-    if (t.b_kind[b] == KIND_INNER) {
+  c.sym.clear();
+  c.hrho.clear();
+  // Breadth-first: the sons of the blocks of one level are generated in block-id
+  // order, so terms and pair lists are appended in block order and both CSR arrays
+  // are filled directly. Pair lists of inner blocks live only for one level.
+  // Pair entries are triples (rho, block tau x rho, block rho x sigma); the blocks of
+  // a son pair follow from the parents' ids because sons of a block are stored
+  // tau-son-major and contiguously: son (i, j) of block x is child0[x] + i * #sons(sigma_x) + j.
+  std::vector<int32_t> cur_ptr{0, 1}, cur_rho{0, 0, 0};  // level 0: the root, rho = I
+  int64_t lev_first = 0;                                  // first block id of the current level
+  auto leaf_pairs = [&](int64_t b, const int32_t* r, int cnt) {
+    for (int i = 0; i < 3 * cnt; ++i) c.hrho.push_back(r[i]);
+    c.hptr[b + 1] = int32_t(c.hrho.size() / 3);
+  };
+  if (t.b_kind[0] != KIND_INNER) leaf_pairs(0, cur_rho.data(), 1);
+  else c.hptr[1] = 0;
+  c.group_ptr_h[1] = 0;
+  for (int lev = 0; lev < t.depth; ++lev) {
+    const int64_t lb = t.level_begin[lev], le = t.level_begin[lev + 1];
+    std::vector<int32_t> nxt_ptr{0}, nxt_rho;
+    int64_t next_expected = t.level_begin[lev + 1];
+    for (int64_t b = lb; b < le; ++b) {
+      if (t.b_kind[b] != KIND_INNER) continue;
+      const int32_t* rb = cur_rho.data() + 3 * cur_ptr[b - lev_first];
+      const int nr = cur_ptr[b - lev_first + 1] - cur_ptr[b - lev_first];
+      const int ns = t.c_nchild[t.b_sigma[b]];
       for (int ci = 0; ci < t.b_nchild[b]; ++ci) {
         const int32_t ch = t.b_child0[b] + ci;
-        const int32_t tau2 = t.b_tau[ch], sig2 = t.b_sigma[ch];
-        auto& terms = per_block_terms[ch];
-        auto& hl = H[ch];
-        for (int32_t rho : H[b]) {
+        if (ch != next_expected) throw Error(HMAT_ERR_INTERNAL, "block order");
+        ++next_expected;
+        const int it = ci / ns, is = ci % ns;  // son indices in tau_b and sigma_b
+        const size_t h0 = nxt_rho.size();
+        for (int q = 0; q < nr; ++q) {
+          const int32_t rho = rb[3 * q], qa = rb[3 * q + 1], qb = rb[3 * q + 2];
           if (t.c_nchild[rho] == 0) {
             // middle cluster is a leaf: both factors are nearfield leaves of the parent level
-            int32_t a_blk = t.find_block(t.b_tau[b], rho);
-            int32_t b_blk = t.find_block(rho, t.b_sigma[b]);
-            if (a_blk < 0 || b_blk < 0) throw Error(HMAT_ERR_INTERNAL, "missing leaf pair");
-            SymTerm s{T_GAP, ch, a_blk, b_blk, t.c_size[rho], t.c_size[rho], 0, -1};
-            terms.push_back(s);
+            c.sym.push_back(SymTerm{T_GAP, ch, qa, qb, t.c_size[rho], t.c_size[rho], 0, -1});
             continue;
           }
-          for (int i = 0; i < t.c_nchild[rho]; ++i) {
+          const int nrho = t.c_nchild[rho];
+          for (int i = 0; i < nrho; ++i) {
             const int32_t r2 = t.c_child0[rho] + i;
-            const int32_t b1 = t.find_block(tau2, r2);
-            const int32_t b2 = t.find_block(r2, sig2);
-            if (b1 < 0 || b2 < 0) throw Error(HMAT_ERR_INTERNAL, "missing son block in restriction");
+            const int32_t b1 = t.b_child0[qa] + it * nrho + i;  // tau' x rho'
+            const int32_t b2 = t.b_child0[qb] + i * ns + is;    // rho' x sigma'
             const bool f1 = t.b_kind[b1] == KIND_F, f2 = t.b_kind[b2] == KIND_F;
             if (f1 && f2) {
               if (c.rank_a(b1) && c.rank_b(b2))
-                terms.push_back(SymTerm{T_FF, ch, b1, b2, c.rank_a(b1), c.rank_b(b2), 0, -1});
+                c.sym.push_back(SymTerm{T_FF, ch, b1, b2, c.rank_a(b1), c.rank_b(b2), 0, -1});
             } else if (f1) {
-              if (c.rank_a(b1)) terms.push_back(SymTerm{T_FH, ch, b1, b2, c.rank_a(b1), c.rank_a(b1), 0, -1});
+              if (c.rank_a(b1)) c.sym.push_back(SymTerm{T_FH, ch, b1, b2, c.rank_a(b1), c.rank_a(b1), 0, -1});
             } else if (f2) {
-              if (c.rank_b(b2)) terms.push_back(SymTerm{T_HF, ch, b1, b2, c.rank_b(b2), c.rank_b(b2), 0, -1});
+              if (c.rank_b(b2)) c.sym.push_back(SymTerm{T_HF, ch, b1, b2, c.rank_b(b2), c.rank_b(b2), 0, -1});
             } else {
-              hl.push_back(r2);
+              nxt_rho.push_back(r2);
+              nxt_rho.push_back(b1);
+              nxt_rho.push_back(b2);
             }
           }
         }
-      }
-      if (b > 0) {
-        std::vector<int32_t>().swap(H[b]);  // parent's list no longer needed except for targets
+        c.group_ptr_h[ch + 1] = int32_t(c.sym.size());
+        const int cnt = int((nxt_rho.size() - h0) / 3);
+        if (t.b_kind[ch] != KIND_INNER) {
+          leaf_pairs(ch, nxt_rho.data() + h0, cnt);
+          nxt_rho.resize(h0);
+        } else {
+          c.hptr[ch + 1] = int32_t(c.hrho.size() / 3);
+        }
+        nxt_ptr.push_back(int32_t(nxt_rho.size() / 3));
       }
     }
+    if (int64_t(nxt_ptr.size()) != t.level_begin[lev + 2] - t.level_begin[lev + 1] + 1)
+      throw Error(HMAT_ERR_INTERNAL, "level size");
+    cur_ptr.swap(nxt_ptr);
+    cur_rho.swap(nxt_rho);
+    lev_first = t.level_begin[lev + 1];
   }
-  // H lists of leaves are needed by the targets; inner lists were released. Rebuild the
-  // CSR from what remains (leaves keep theirs).
-  for (int64_t b = 0; b < nb; ++b) {
-    c.group_ptr_h[b + 1] = c.group_ptr_h[b] + int32_t(per_block_terms[b].size());
-    c.hptr[b + 1] = c.hptr[b] + int32_t(t.b_kind[b] == KIND_INNER ? 0 : H[b].size());
-  }
-  c.sym.reserve(c.group_ptr_h[nb]);
-  for (int64_t b = 0; b < nb; ++b)
-    for (auto& s : per_block_terms[b]) c.sym.push_back(s);
-  c.hrho.reserve(c.hptr[nb]);
-  for (int64_t b = 0; b < nb; ++b)
-    if (t.b_kind[b] != KIND_INNER)
-      for (int32_t r : H[b]) c.hrho.push_back(r);
 }
 
-// ------------------------------------------------------------------ creation of terms
-struct Creation {
+// ------------------------------------------------------------------ subtree task lists
+// Tasks of one launch pair (leaf reductions, then output expansion). The device
+// enumerates the work items from two prefix sums: leaves of each task's subtree
+// (depth-first range) and leaf clusters of each task's output cluster.
+struct TaskList {
   std::vector<Task> tasks;
-  std::vector<LeafItem> leaf_items;
-  std::vector<RowItem> row_items;
+  std::vector<int64_t> lpre{0}, rpre{0};
+  DevBuf<Task> d_tasks;
+  DevBuf<int64_t> d_lpre, d_rpre;
   int64_t ws_len = 0;
+  void add(const Ctx& c, const Task& tk, bool expand) {
+    const Tree& t = *c.t;
+    tasks.push_back(tk);
+    lpre.push_back(lpre.back() + (c.dfs.hi[tk.q] - c.dfs.lo[tk.q]));
+    const int32_t outc = tk.trans ? t.b_sigma[tk.q] : t.b_tau[tk.q];
+    rpre.push_back(rpre.back() + (expand ? (t.c_lc_end[outc] - t.c_lc_begin[outc]) : 0));
+  }
+  int ntask() const { return int(tasks.size()); }
+  void upload(hipStream_t s) {
+    d_tasks.upload(tasks, s);
+    d_lpre.upload(lpre, s);
+    d_rpre.upload(rpre, s);
+  }
 };
 
 void add_subtree_rows(const Tree& t, int32_t owner, int32_t cluster, std::vector<RowItem>& rows) {
@@ -304,16 +351,26 @@ void account(hmat_stats& st, int kind, const Coef& k, double w) {
   st.kern_flops[kind] += k.f * w;
 }
 
-// leaf items of a subtree task; returns the workspace (doubles) its leaf products need
-int64_t add_subtree_leaves(const Ctx& c, int32_t owner, int mat, int32_t q, std::vector<LeafItem>& items) {
-  const Tree& t = *c.t;
-  const HMat* M = mat ? c.B : c.A;
+// workspace (doubles) the leaf reductions of a subtree task need
+int64_t subtree_ws(const Ctx& c, int mat, int32_t q) {
   const DevMat& dm = mat ? c.db : c.da;
-  for (int32_t i = c.dfs.lo[q]; i < c.dfs.hi[q]; ++i) {
-    int32_t b = c.dfs.dfs_block[i];
-    if (t.b_kind[b] == KIND_F && M->rank[b] > 0) items.push_back(LeafItem{owner, b});
-  }
   return (dm.hkpref[c.dfs.hi[q]] - dm.hkpref[c.dfs.lo[q]]) * PW;
+}
+
+// Leaf reductions (and expansions) of a task list; X and widths of target tasks come from td.
+void run_tasks(Ctx& c, TaskList& L, const TDesc* td, double* ws, bool expand) {
+  if (L.tasks.empty()) return;
+  if (L.lpre.back() > 0) {
+    c.timer.begin(K_LEAF);
+    launch_leaf_reduce(L.d_lpre.p, L.ntask(), L.lpre.back(), L.d_tasks.p, td, c.d_dfs_block.p, c.tv, c.ma, c.mb, ws,
+                       c.s);
+    c.timer.end();
+  }
+  if (expand && L.rpre.back() > 0) {
+    c.timer.begin(K_EXPAND);
+    launch_subtree_expand(L.d_rpre.p, L.ntask(), L.rpre.back(), L.d_tasks.p, td, c.tv, c.ma, c.mb, ws, c.s);
+    c.timer.end();
+  }
 }
 
 void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& pool_out) {
@@ -328,10 +385,15 @@ void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& poo
     else if (st.type == T_HF) st.data_off = pos, pos += int64_t(st.kl) * c.m_of(st.child);
     else st.data_off = -1;
   }
-  pool_out.alloc(size_t(std::max<int64_t>(pos, 1)));
+  if (pool_out.n < size_t(std::max<int64_t>(pos, 1))) {  // callers may pass a pool sized for several calls
+    const double ta = now_seconds();
+    pool_out.alloc(size_t(std::max<int64_t>(pos, 1)));
+    c.st.t_host[4] += now_seconds() - ta;
+  }
   double* P = pool_out.p;
-  // FF cores: leaf products only, written straight into the pool
-  Creation ff, fh;
+  const double th0 = now_seconds();
+  // FF cores: leaf reductions R_A^T L_B written straight into the pool
+  TaskList ff, fh;
   for (int32_t i : which) {
     const SymTerm& st = c.sym[i];
     if (st.type == T_FF) {
@@ -348,8 +410,7 @@ void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& poo
         tk.w = std::min(PW, st.kr - j0);
         tk.lo = c.dfs.lo[st.a_blk];
         tk.tws = st.data_off + int64_t(j0) * st.kl;
-        ff.leaf_items.push_back(LeafItem{int32_t(ff.tasks.size()), st.a_blk});
-        ff.tasks.push_back(tk);
+        ff.add(c, tk, false);
         {
           const double nr = t.c_size[rho], w = tk.w;
           Coef k{8 * nr * st.kl, 8 * (nr + st.kl), 2 * nr * st.kl};
@@ -379,10 +440,8 @@ void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& poo
         tk.w = std::min(PW, st.kl - j0);
         tk.lo = c.dfs.lo[tk.q];
         tk.tws = fh.ws_len;
-        const int32_t owner = int32_t(fh.tasks.size());
-        fh.ws_len += add_subtree_leaves(c, owner, tk.mat, tk.q, fh.leaf_items);
-        add_subtree_rows(t, owner, isfh ? t.b_sigma[tk.q] : t.b_tau[tk.q], fh.row_items);
-        fh.tasks.push_back(tk);
+        fh.ws_len += subtree_ws(c, tk.mat, tk.q);
+        fh.add(c, tk, true);
         {
           Coef kl, ke;
           subtree_coef(c, tk.mat, tk.q, tk.trans, kl, ke);
@@ -394,32 +453,19 @@ void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& poo
       }
     }
   }
-  if (!ff.tasks.empty()) {
-    DevBuf<Task> dt;
-    dt.upload(ff.tasks, s);
-    DevBuf<LeafItem> dl;
-    dl.upload(ff.leaf_items, s);
-    c.timer.begin(K_LEAF);
-    launch_leaf_p1(dl.p, ff.leaf_items.size(), dt.p, nullptr, c.tv, c.ma, c.mb, P, s);
-    c.timer.end();
-    HM_CHECK_HIP(hipStreamSynchronize(s));
-  }
+  c.st.t_host[1] += now_seconds() - th0;
+  double tu = now_seconds();
+  if (!ff.tasks.empty()) ff.upload(s);
+  if (!fh.tasks.empty()) fh.upload(s);
+  c.st.t_host[5] += now_seconds() - tu;
+  tu = now_seconds();
+  if (!ff.tasks.empty()) run_tasks(c, ff, nullptr, P, false);
   if (!fh.tasks.empty()) {
-    DevBuf<Task> dt;
-    dt.upload(fh.tasks, s);
-    DevBuf<LeafItem> dl;
-    dl.upload(fh.leaf_items, s);
-    DevBuf<RowItem> dr;
-    dr.upload(fh.row_items, s);
     DevBuf<double> ws(size_t(std::max<int64_t>(fh.ws_len, 1)));
-    c.timer.begin(K_LEAF);
-    launch_leaf_p1(dl.p, fh.leaf_items.size(), dt.p, nullptr, c.tv, c.ma, c.mb, ws.p, s);
-    c.timer.end();
-    c.timer.begin(K_EXPAND);
-    launch_subtree_p2(dr.p, fh.row_items.size(), dt.p, nullptr, c.tv, c.ma, c.mb, ws.p, s);
-    c.timer.end();
-    HM_CHECK_HIP(hipStreamSynchronize(s));
+    run_tasks(c, fh, nullptr, ws.p, true);
   }
+  HM_CHECK_HIP(hipStreamSynchronize(s));
+  c.st.t_host[6] += now_seconds() - tu;
   // device descriptors of these terms
   for (int32_t i : which) {
     const SymTerm& st = c.sym[i];
@@ -474,27 +520,50 @@ void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& poo
   }
 }
 
+// Device descriptors of the terms in `which` (only these changed since the last call).
+void publish_terms(Ctx& c, const std::vector<int32_t>& which) {
+  const double t0 = now_seconds();
+  struct Acc {
+    Ctx& c;
+    double t0;
+    ~Acc() { c.st.t_host[7] += now_seconds() - t0; }
+  } acc{c, t0};
+  if (c.terms.n < c.hterms.size()) c.terms.alloc(c.hterms.size());
+  if (which.empty()) return;
+  std::vector<Term> packed(which.size());
+  for (size_t i = 0; i < which.size(); ++i) packed[i] = c.hterms[which[i]];
+  DevBuf<int32_t> ids;
+  ids.upload(which, c.s);
+  DevBuf<Term> src;
+  src.upload(packed, c.s);
+  launch_scatter_terms(ids.p, src.p, c.terms.p, int64_t(which.size()), c.s);
+  HM_CHECK_HIP(hipStreamSynchronize(c.s));
+}
+
 // ------------------------------------------------------------------ target chunks
 struct Chunk {
   std::vector<int32_t> blocks;  // target blocks
   std::vector<TInfo> info;
   std::vector<HPair> pairs;
-  std::vector<Task> tasks_f, tasks_t;  // 2 per pair: stage 1, stage 2
-  std::vector<LeafItem> l1f, l2f, l1t, l2t;
-  std::vector<RowItem> r1f, r2f, r1t, r2t;
+  // pair stages: forward B-side (1f) then A-side (2f); transposed A-side (1t) then B-side (2t)
+  TaskList t1f, t2f, t1t, t2t;
   std::vector<TermItem> term_items;
-  std::vector<RowItem> gf, gt;  // gather items forward / transposed
-  int64_t vlen = 0, tws_f = 0, tws_t = 0, pair_len = 0;
+  std::vector<RowItem> gf, gt;  // gather items forward / transposed (large targets)
+  // pair temporaries start at offset PW so that no stage-2 input offset is 0 (0 = "input from
+  // the target's pass descriptor")
+  int64_t vlen = 0, tws_f = 0, tws_t = 0, pair_len = PW;
   // device
   DevBuf<TInfo> d_info;
   DevBuf<HPair> d_pairs;
-  DevBuf<Task> d_tasks_f, d_tasks_t;
-  DevBuf<LeafItem> d_l1f, d_l2f, d_l1t, d_l2t;
-  DevBuf<RowItem> d_r1f, d_r2f, d_r1t, d_r2t, d_gf, d_gt;
+  DevBuf<RowItem> d_gf, d_gt;
   DevBuf<TermItem> d_terms;
   DevBuf<double> vbuf, wsf, wst, pairbuf;
   DevBuf<TDesc> d_td;
   std::vector<Coef> coef[4][2];  // per kernel family and direction, per target
+  std::vector<int32_t> small;    // targets applied by the one-wave fused kernel
+  std::vector<int32_t> small4;   // targets applied by the four-wave fused kernel
+  std::vector<uint8_t> is_small;
+  DevBuf<int32_t> d_small, d_small4;
 };
 
 int64_t target_cost(const Ctx& c, int32_t b, bool far, const Opts& o, int cap) {
@@ -506,8 +575,7 @@ int64_t target_cost(const Ctx& c, int32_t b, bool far, const Opts& o, int cap) {
       v += int64_t(std::max(c.sym[i].kl, c.sym[i].kr)) * PW;
   int64_t pr = 0;
   for (int32_t j = c.hptr[b]; j < c.hptr[b + 1]; ++j) {
-    int32_t rho = c.hrho[j];
-    int32_t qa = t.find_block(t.b_tau[b], rho), qb = t.find_block(rho, t.b_sigma[b]);
+    int32_t rho = c.hrho[3 * j], qa = c.hrho[3 * j + 1], qb = c.hrho[3 * j + 2];
     pr += (t.c_size[rho] + std::max(m, n)) * PW;
     pr += 2 * (c.da.hkpref[c.dfs.hi[qa]] - c.da.hkpref[c.dfs.lo[qa]] + c.db.hkpref[c.dfs.hi[qb]] -
                c.db.hkpref[c.dfs.lo[qb]]) * PW;
@@ -522,17 +590,25 @@ void build_chunk(const Ctx& c, Chunk& ch) {
   ch.info.resize(nt);
   for (int k = 0; k < 4; ++k)
     for (int d = 0; d < 2; ++d) ch.coef[k][d].assign(nt, Coef{});
+  ch.is_small.assign(nt, 0);
   for (int i = 0; i < nt; ++i) {
     const int32_t b = ch.blocks[i];
     TInfo& ti = ch.info[i];
     ti.block = b;
     ti.vbase = ch.vlen;
     const double mt = t.c_size[t.b_tau[b]], nt_ = t.c_size[t.b_sigma[b]];
+    const bool small1 = mt <= FUSED_MAX && nt_ <= FUSED_MAX;
+    const bool small = mt <= FUSED4_MAX && nt_ <= FUSED4_MAX;
+    ch.is_small[i] = small;
+    if (small1) ch.small.push_back(i);
+    else if (small) ch.small4.push_back(i);
     double skl = 0, skr = 0;
     for (int32_t a = b; a >= 0; a = t.b_parent[a])
       for (int32_t j = c.group_ptr_h[a]; j < c.group_ptr_h[a + 1]; ++j) {
-        ch.term_items.push_back(TermItem{i, j, ch.vlen});
-        ch.vlen += int64_t(std::max(c.sym[j].kl, c.sym[j].kr)) * PW;
+        if (!small) {
+          ch.term_items.push_back(TermItem{i, j, ch.vlen});
+          ch.vlen += int64_t(std::max(c.sym[j].kl, c.sym[j].kr)) * PW;
+        }
         const SymTerm& sy = c.sym[j];
         const double core = sy.type == T_FF ? double(sy.kl) * sy.kr : 0.0;
         Coef& f = ch.coef[K_TERM][0][i];
@@ -563,8 +639,7 @@ void build_chunk(const Ctx& c, Chunk& ch) {
     const int32_t tau = t.b_tau[b], sig = t.b_sigma[b];
     const int32_t m = t.c_size[tau], n = t.c_size[sig];
     for (int32_t j = c.hptr[b]; j < c.hptr[b + 1]; ++j) {
-      const int32_t rho = c.hrho[j];
-      const int32_t qa = t.find_block(tau, rho), qb = t.find_block(rho, sig);
+      const int32_t rho = c.hrho[3 * j], qa = c.hrho[3 * j + 1], qb = c.hrho[3 * j + 2];
       if (qa < 0 || qb < 0) throw Error(HMAT_ERR_INTERNAL, "pair blocks missing");
       subtree_coef(c, 1, qb, 0, ch.coef[K_LEAF][0][i], ch.coef[K_EXPAND][0][i]);
       subtree_coef(c, 0, qa, 0, ch.coef[K_LEAF][0][i], ch.coef[K_EXPAND][0][i]);
@@ -574,99 +649,56 @@ void build_chunk(const Ctx& c, Chunk& ch) {
       ch.pair_len += int64_t(t.c_size[rho]) * PW;
       const int64_t off2 = ch.pair_len;
       ch.pair_len += int64_t(std::max(m, n)) * PW;
-      const int32_t p = int32_t(ch.pairs.size());
       ch.pairs.push_back(HPair{reinterpret_cast<double*>(off2)});  // offset, rebased on upload
-      // forward: stage 1 B[rho, sigma] X -> temp1; stage 2 A[tau, rho] temp1 -> temp2
-      {
-        Task s1{}, s2{};
-        s1.X = nullptr;
-        s1.Y = reinterpret_cast<double*>(off1);
-        s1.ldy = t.c_size[rho];
-        s1.mat = 1;
-        s1.q = qb;
-        s1.trans = 0;
-        s1.t = i;
-        s1.lo = c.dfs.lo[qb];
-        s1.tws = ch.tws_f;
-        ch.tws_f += add_subtree_leaves(c, 2 * p, 1, qb, ch.l1f);
-        add_subtree_rows(t, 2 * p, rho, ch.r1f);
-        s2.X = reinterpret_cast<double*>(off1);
-        s2.ldx = t.c_size[rho];
-        s2.Y = reinterpret_cast<double*>(off2);
-        s2.ldy = m;
-        s2.mat = 0;
-        s2.q = qa;
-        s2.trans = 0;
-        s2.t = i;
-        s2.lo = c.dfs.lo[qa];
-        s2.tws = ch.tws_f;
-        ch.tws_f += add_subtree_leaves(c, 2 * p + 1, 0, qa, ch.l2f);
-        add_subtree_rows(t, 2 * p + 1, tau, ch.r2f);
-        ch.tasks_f.push_back(s1);
-        ch.tasks_f.push_back(s2);
-      }
-      // transposed: stage 1 A[tau, rho]^T X -> temp1; stage 2 B[rho, sigma]^T temp1 -> temp2
-      {
-        Task s1{}, s2{};
-        s1.X = nullptr;
-        s1.Y = reinterpret_cast<double*>(off1);
-        s1.ldy = t.c_size[rho];
-        s1.mat = 0;
-        s1.q = qa;
-        s1.trans = 1;
-        s1.t = i;
-        s1.lo = c.dfs.lo[qa];
-        s1.tws = ch.tws_t;
-        ch.tws_t += add_subtree_leaves(c, 2 * p, 0, qa, ch.l1t);
-        add_subtree_rows(t, 2 * p, rho, ch.r1t);
-        s2.X = reinterpret_cast<double*>(off1);
-        s2.ldx = t.c_size[rho];
-        s2.Y = reinterpret_cast<double*>(off2);
-        s2.ldy = n;
-        s2.mat = 1;
-        s2.q = qb;
-        s2.trans = 1;
-        s2.t = i;
-        s2.lo = c.dfs.lo[qb];
-        s2.tws = ch.tws_t;
-        ch.tws_t += add_subtree_leaves(c, 2 * p + 1, 1, qb, ch.l2t);
-        add_subtree_rows(t, 2 * p + 1, sig, ch.r2t);
-        ch.tasks_t.push_back(s1);
-        ch.tasks_t.push_back(s2);
-      }
+      auto stage = [&](TaskList& L, int64_t& tws, int mat, int32_t q, int trans, int64_t xoff, int64_t yoff,
+                       int ldy) {
+        Task tk{};
+        tk.X = xoff < 0 ? nullptr : reinterpret_cast<double*>(xoff);
+        tk.ldx = t.c_size[rho];
+        tk.Y = reinterpret_cast<double*>(yoff);
+        tk.ldy = ldy;
+        tk.mat = mat;
+        tk.q = q;
+        tk.trans = trans;
+        tk.t = i;
+        tk.lo = c.dfs.lo[q];
+        tk.tws = tws;
+        tws += subtree_ws(c, mat, q);
+        L.add(c, tk, true);
+      };
+      // forward: B[rho, sigma] X -> temp1, then A[tau, rho] temp1 -> temp2
+      stage(ch.t1f, ch.tws_f, 1, qb, 0, -1, off1, t.c_size[rho]);
+      stage(ch.t2f, ch.tws_f, 0, qa, 0, off1, off2, m);
+      // transposed: A[tau, rho]^T X -> temp1, then B[rho, sigma]^T temp1 -> temp2
+      stage(ch.t1t, ch.tws_t, 0, qa, 1, -1, off1, t.c_size[rho]);
+      stage(ch.t2t, ch.tws_t, 1, qb, 1, off1, off2, n);
     }
     ti.hp_end = int32_t(ch.pairs.size());
-    add_subtree_rows(t, i, tau, ch.gf);
-    add_subtree_rows(t, i, sig, ch.gt);
+    if (!small) {
+      add_subtree_rows(t, i, tau, ch.gf);
+      add_subtree_rows(t, i, sig, ch.gt);
+    }
   }
 }
 
 void upload_chunk(Chunk& ch, hipStream_t s) {
   ch.pairbuf.alloc(size_t(std::max<int64_t>(ch.pair_len, 1)));
   double* base = ch.pairbuf.p;
-  auto rebase = [&](double* p) { return base + reinterpret_cast<intptr_t>(p); };
+  auto rebase = [&](const double* p) { return base + reinterpret_cast<intptr_t>(p); };
   for (auto& hp : ch.pairs) hp.temp2 = rebase(hp.temp2);
-  for (auto* tl : {&ch.tasks_f, &ch.tasks_t})
-    for (size_t i = 0; i < tl->size(); ++i) {
-      Task& tk = (*tl)[i];
+  for (auto* L : {&ch.t1f, &ch.t2f, &ch.t1t, &ch.t2t})
+    for (Task& tk : L->tasks) {
       tk.Y = rebase(tk.Y);
-      if (i % 2 == 1) tk.X = rebase(const_cast<double*>(tk.X));
+      if (tk.X) tk.X = rebase(tk.X);
     }
   ch.d_info.upload(ch.info, s);
   ch.d_pairs.upload(ch.pairs, s);
-  ch.d_tasks_f.upload(ch.tasks_f, s);
-  ch.d_tasks_t.upload(ch.tasks_t, s);
-  ch.d_l1f.upload(ch.l1f, s);
-  ch.d_l2f.upload(ch.l2f, s);
-  ch.d_l1t.upload(ch.l1t, s);
-  ch.d_l2t.upload(ch.l2t, s);
-  ch.d_r1f.upload(ch.r1f, s);
-  ch.d_r2f.upload(ch.r2f, s);
-  ch.d_r1t.upload(ch.r1t, s);
-  ch.d_r2t.upload(ch.r2t, s);
+  for (auto* L : {&ch.t1f, &ch.t2f, &ch.t1t, &ch.t2t}) L->upload(s);
   ch.d_gf.upload(ch.gf, s);
   ch.d_gt.upload(ch.gt, s);
   ch.d_terms.upload(ch.term_items, s);
+  ch.d_small.upload(ch.small, s);
+  ch.d_small4.upload(ch.small4, s);
   ch.vbuf.alloc(size_t(std::max<int64_t>(ch.vlen, 1)));
   ch.wsf.alloc(size_t(std::max<int64_t>(ch.tws_f, 1)));
   ch.wst.alloc(size_t(std::max<int64_t>(ch.tws_t, 1)));
@@ -680,43 +712,42 @@ void run_pass(Ctx& c, Chunk& ch, const std::vector<TDesc>& td, bool trans) {
   const TDesc* dtd = ch.d_td.p;
   const int d = trans ? 1 : 0;
   for (size_t i = 0; i < td.size(); ++i)
-    if (td[i].w)
-      for (int k = 0; k < 4; ++k) account(c.st, k, ch.coef[k][d][i], td[i].w);
-  auto& tasks = trans ? ch.d_tasks_t : ch.d_tasks_f;
-  auto& ws = trans ? ch.wst : ch.wsf;
-  auto& l1 = trans ? ch.d_l1t : ch.d_l1f;
-  auto& l2 = trans ? ch.d_l2t : ch.d_l2f;
-  auto& r1 = trans ? ch.d_r1t : ch.d_r1f;
-  auto& r2 = trans ? ch.d_r2t : ch.d_r2f;
-  const size_t nl1 = trans ? ch.l1t.size() : ch.l1f.size(), nl2 = trans ? ch.l2t.size() : ch.l2f.size();
-  const size_t nr1 = trans ? ch.r1t.size() : ch.r1f.size(), nr2 = trans ? ch.r2t.size() : ch.r2f.size();
-  c.timer.begin(K_TERM);
-  launch_term_p1(ch.d_terms.p, ch.term_items.size(), dtd, ch.d_info.p, c.tv, ch.vbuf.p, s);
-  c.timer.end();
-  if (nl1) {
-    c.timer.begin(K_LEAF);
-    launch_leaf_p1(l1.p, nl1, tasks.p, dtd, c.tv, c.ma, c.mb, ws.p, s);
+    if (td[i].w) {
+      account(c.st, K_LEAF, ch.coef[K_LEAF][d][i], td[i].w);
+      account(c.st, K_EXPAND, ch.coef[K_EXPAND][d][i], td[i].w);
+      if (ch.is_small[i]) {
+        account(c.st, K_FUSED, ch.coef[K_TERM][d][i], td[i].w);
+        account(c.st, K_FUSED, ch.coef[K_GATHER][d][i], td[i].w);
+      } else {
+        account(c.st, K_TERM, ch.coef[K_TERM][d][i], td[i].w);
+        account(c.st, K_GATHER, ch.coef[K_GATHER][d][i], td[i].w);
+      }
+    }
+  if (!trans) {
+    run_tasks(c, ch.t1f, dtd, ch.wsf.p, true);
+    run_tasks(c, ch.t2f, dtd, ch.wsf.p, true);
+  } else {
+    run_tasks(c, ch.t1t, dtd, ch.wst.p, true);
+    run_tasks(c, ch.t2t, dtd, ch.wst.p, true);
+  }
+  if (!ch.term_items.empty()) {
+    c.timer.begin(K_TERM);
+    launch_term_reduce(ch.d_terms.p, ch.term_items.size(), dtd, ch.d_info.p, c.tv, ch.vbuf.p, s);
     c.timer.end();
   }
-  if (nr1) {
-    c.timer.begin(K_EXPAND);
-    launch_subtree_p2(r1.p, nr1, tasks.p, dtd, c.tv, c.ma, c.mb, ws.p, s);
+  const size_t ng = trans ? ch.gt.size() : ch.gf.size();
+  if (ng) {
+    c.timer.begin(K_GATHER);
+    launch_gather_mfma(trans ? ch.d_gt.p : ch.d_gf.p, ng, dtd, ch.d_info.p, ch.d_pairs.p, c.tv, ch.vbuf.p, s);
     c.timer.end();
   }
-  if (nl2) {
-    c.timer.begin(K_LEAF);
-    launch_leaf_p1(l2.p, nl2, tasks.p, dtd, c.tv, c.ma, c.mb, ws.p, s);
+  if (!ch.small.empty() || !ch.small4.empty()) {
+    c.timer.begin(K_FUSED);
+    if (!ch.small.empty()) launch_fused_terms(ch.d_small.p, ch.small.size(), dtd, ch.d_info.p, ch.d_pairs.p, c.tv, s);
+    if (!ch.small4.empty())
+      launch_fused_terms4(ch.d_small4.p, ch.small4.size(), dtd, ch.d_info.p, ch.d_pairs.p, c.tv, s);
     c.timer.end();
   }
-  if (nr2) {
-    c.timer.begin(K_EXPAND);
-    launch_subtree_p2(r2.p, nr2, tasks.p, dtd, c.tv, c.ma, c.mb, ws.p, s);
-    c.timer.end();
-  }
-  c.timer.begin(K_GATHER);
-  launch_gather(trans ? ch.d_gt.p : ch.d_gf.p, trans ? ch.gt.size() : ch.gf.size(), dtd, ch.d_info.p,
-                ch.d_pairs.p, c.tv, ch.vbuf.p, s);
-  c.timer.end();
 }
 
 struct FarOut {
@@ -842,8 +873,10 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
     }
   };
   auto fetch = [&]() {
+    const double t0 = now_seconds();
     HM_CHECK_HIP(hipMemcpyAsync(h.data(), dt.p, sizeof(CTarget) * nt, hipMemcpyDeviceToHost, s));
     HM_CHECK_HIP(hipStreamSynchronize(s));
+    c.st.t_host[3] += now_seconds() - t0;
   };
   std::vector<int> all(nt, 1);
   double t0 = now_seconds();
@@ -1012,6 +1045,7 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   c.eps = eps;
   c.opts = opts;
   hipStream_t s = c.s;
+  set_current_stream(s);
   t->ensure_device(s);
 
   // plan
@@ -1024,15 +1058,20 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   build_subsums(c, B, c.sb);
   c.timer.on = opts.o.time_kernels != 0;
   c.timer.s = s;
-  symbolic(c);
+  {
+    const double t0 = now_seconds();
+    symbolic(c);
+    c.st.t_host[0] += now_seconds() - t0;
+  }
   c.b_parent.upload(t->b_parent, s);
   c.b_dfs.upload(c.dfs.dfs_of_block, s);
+  c.d_dfs_block.upload(c.dfs.dfs_block, s);
   c.group_ptr.upload(c.group_ptr_h, s);
   c.hterms.assign(c.sym.size(), Term{});
   c.tv = TreeView{t->dev->c_begin.p, t->dev->c_size.p, t->dev->c_parent.p, t->dev->leaf_clusters.p,
                   t->dev->b_tau.p, t->dev->b_sigma.p, t->dev->b_kind.p, c.b_parent.p, c.b_dfs.p,
                   t->dev->brow_ptr.p, t->dev->brow_blk.p, t->dev->bcol_ptr.p, t->dev->bcol_blk.p,
-                  c.group_ptr.p, nullptr};
+                  c.group_ptr.p, nullptr, t->dev->c_lc_begin.p};
   c.st.t_plan = now_seconds() - t_start;
 
   // memory of the data each term creates, and the level of the block it belongs to
@@ -1117,38 +1156,62 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   const int cap_est = std::min(64, opts.o.b0 + opts.o.max_growth * opts.o.probes);
   std::vector<FarOut> outs;
 
-  auto process_targets = [&](const std::vector<int32_t>& near, const std::vector<int32_t>& far) {
-    double tn = now_seconds();
-    for (size_t i = 0; i < near.size();) {
-      Chunk ch;
+  // Targets are processed in chunks; the host work lists of chunk k+1 are built on a
+  // worker thread while the device runs chunk k.
+  auto partition = [&](const std::vector<int32_t>& list, bool far) {
+    std::vector<std::vector<int32_t>> parts;
+    for (size_t i = 0; i < list.size();) {
+      std::vector<int32_t> blk;
       int64_t used = 0;
-      while (i < near.size()) {
-        int64_t cst = target_cost(c, near[i], false, opts, cap_est);
-        if (!ch.blocks.empty() && used + cst > budget) break;
+      while (i < list.size()) {
+        int64_t cst = target_cost(c, list[i], far, opts, cap_est);
+        if (!blk.empty() && used + cst > budget) break;
         used += cst;
-        ch.blocks.push_back(near[i++]);
+        blk.push_back(list[i++]);
       }
-      build_chunk(c, ch);
-      upload_chunk(ch, s);
-      std::vector<int64_t> coff;
-      for (int32_t b : ch.blocks) coff.push_back(near_off[b]);
-      evaluate_chunk(c, ch, near_buf.p, coff);
+      parts.push_back(std::move(blk));
     }
-    c.st.t_near += now_seconds() - tn;
-    for (size_t i = 0; i < far.size();) {
-      Chunk ch;
-      int64_t used = 0;
-      while (i < far.size()) {
-        int64_t cst = target_cost(c, far[i], true, opts, cap_est);
-        if (!ch.blocks.empty() && used + cst > budget) break;
-        used += cst;
-        ch.blocks.push_back(far[i++]);
-      }
-      build_chunk(c, ch);
+    return parts;
+  };
+  auto process_targets = [&](const std::vector<int32_t>& near, const std::vector<int32_t>& far) {
+    struct Job {
+      bool far;
+      std::vector<int32_t> blocks;
+    };
+    std::vector<Job> jobs;
+    const double tp = now_seconds();
+    for (auto& p : partition(near, false)) jobs.push_back(Job{false, std::move(p)});
+    for (auto& p : partition(far, true)) jobs.push_back(Job{true, std::move(p)});
+    c.st.t_host[2] += now_seconds() - tp;
+    auto build = [&c](std::unique_ptr<Chunk> ch) {
+      build_chunk(c, *ch);
+      return ch;
+    };
+    std::future<std::unique_ptr<Chunk>> next;
+    auto launch_build = [&](size_t k) {
+      auto ch = std::make_unique<Chunk>();
+      ch->blocks = jobs[k].blocks;
+      next = std::async(std::launch::async, build, std::move(ch));
+    };
+    if (!jobs.empty()) launch_build(0);
+    for (size_t k = 0; k < jobs.size(); ++k) {
+      const double th = now_seconds();
+      std::unique_ptr<Chunk> chp = next.get();
+      if (k + 1 < jobs.size()) launch_build(k + 1);
+      Chunk& ch = *chp;
       upload_chunk(ch, s);
-      std::vector<int32_t> w0(ch.blocks.size(), opts.o.b0);
-      outs.emplace_back();
-      compress_chunk(c, ch, w0, outs.back());
+      c.st.t_host[2] += now_seconds() - th;
+      if (!jobs[k].far) {
+        double tn = now_seconds();
+        std::vector<int64_t> coff;
+        for (int32_t b : ch.blocks) coff.push_back(near_off[b]);
+        evaluate_chunk(c, ch, near_buf.p, coff);
+        c.st.t_near += now_seconds() - tn;
+      } else {
+        std::vector<int32_t> w0(ch.blocks.size(), opts.o.b0);
+        outs.emplace_back();
+        compress_chunk(c, ch, w0, outs.back());
+      }
     }
   };
 
@@ -1160,7 +1223,7 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   {
     double tc = now_seconds();
     create_terms(c, gterms, global_pool);
-    c.terms.upload(c.hterms, s);
+    publish_terms(c, gterms);
     c.tv.terms = c.terms.p;
     c.st.t_restrict += now_seconds() - tc;
   }
@@ -1183,11 +1246,23 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
       if (t->b_level[b] > L0) bnear[batch_of[root0[b]]].push_back(b);
     for (int32_t b : far_all)
       if (t->b_level[b] > L0) bfar[batch_of[root0[b]]].push_back(b);
+    // one pool, sized for the largest batch, serves every batch in turn
+    int64_t maxpool = 1;
     for (int k = 0; k < nbatch; ++k) {
-      DevBuf<double> batch_pool;
+      int64_t sz = 0;
+      for (int32_t i : bterms[k]) sz += tmem[i] / 8;
+      maxpool = std::max(maxpool, sz);
+    }
+    DevBuf<double> batch_pool;
+    {
+      const double ta = now_seconds();
+      batch_pool.alloc(size_t(maxpool));
+      c.st.t_host[4] += now_seconds() - ta;
+    }
+    for (int k = 0; k < nbatch; ++k) {
       double tc = now_seconds();
       create_terms(c, bterms[k], batch_pool);
-      c.terms.upload(c.hterms, s);
+      publish_terms(c, bterms[k]);
       c.tv.terms = c.terms.p;
       c.st.t_restrict += now_seconds() - tc;
       process_targets(bnear[k], bfar[k]);

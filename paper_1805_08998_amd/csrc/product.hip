@@ -7,12 +7,15 @@
 // terms are views into the factor pools (restriction by index shift), the
 // pairs are products with whole subtrees of A and B (Algorithm 2 on a block).
 //
-// Work decomposition (one 64-lane wave per work item, PW = 16 columns per pass):
-//   k_term_p1   per (target, term): V = core (R^T X)        (reduction over input rows)
-//   k_leaf_p1   per (subtree task, low-rank leaf): T = R^T X (or L^T X)
-//   k_subtree_p2 per (subtree task, output leaf cluster): Y = sum over the
+// Work decomposition (64-lane waves, PW = 16 columns per pass, all products on
+// v_mfma_f64_16x16x4f64):
+//   k_fused_terms / k_fused_terms4  per target with clusters of <= 64 / <= 256 rows:
+//               Y = sum_i P_i (core_i (M_i^T X)) + sum_j pair_j in one kernel
+//   k_term_reduce per (large target, term): V = core (M^T X)
+//   k_gather_mfma per (large target, output leaf cluster): Y = sum_i P_i V_i + sum_j pair_j
+//   k_leaf_reduce per (subtree task, low-rank leaf): T = R^T X (or L^T X)
+//   k_subtree_expand per (subtree task, output leaf cluster): Y = sum over the
 //               leaves whose rows contain it of L T or D X (or the transposes)
-//   k_gather    per (target, output leaf cluster): Y = sum_i L_i V_i + sum_j pair_j
 // Every output row is written by exactly one work item, in a fixed order, so
 // results do not depend on scheduling.
 #include "product_kernels.h"
@@ -20,126 +23,6 @@
 #include "hmat_internal.h"
 
 namespace hm {
-
-// ---------------------------------------------------------------- wave helpers
-// Us[c * PW + col] = sum_r M(r, c) X(r, col) for c < k, col < w.
-// M(r, c) = mtrans ? M[c + r * ldm] : M[r + c * ldm].
-// X(r, col) = xident ? (r == xc0 + col) : X[r + col * ldx].
-__device__ void reduce_wave(const double* __restrict__ M, int ldm, int mtrans, int rows, int k,
-                            const double* __restrict__ X, int ldx, int xident, int xc0, int w,
-                            double* Us) {
-  const int lane = threadIdx.x;
-  const int G = k >= 64 ? 1 : 64 / k;
-  const int c = lane % k, g = lane / k;
-  const bool act = g < G;
-  double acc[PW];
-#pragma unroll
-  for (int s = 0; s < PW; ++s) acc[s] = 0.0;
-  if (act) {
-    if (xident) {
-#pragma unroll
-      for (int s = 0; s < PW; ++s) {
-        int col = g + s * G;
-        int r = xc0 + col;
-        if (col < w && r >= 0 && r < rows) acc[s] = mtrans ? M[c + int64_t(r) * ldm] : M[r + int64_t(c) * ldm];
-      }
-    } else if (mtrans) {
-      for (int r = 0; r < rows; ++r) {
-        double mv = M[c + int64_t(r) * ldm];
-#pragma unroll
-        for (int s = 0; s < PW; ++s) {
-          int col = g + s * G;
-          if (col < w) acc[s] += mv * X[r + int64_t(col) * ldx];
-        }
-      }
-    } else {
-      const double* Mc = M + int64_t(c) * ldm;
-      for (int r = 0; r < rows; ++r) {
-        double mv = Mc[r];
-#pragma unroll
-        for (int s = 0; s < PW; ++s) {
-          int col = g + s * G;
-          if (col < w) acc[s] += mv * X[r + int64_t(col) * ldx];
-        }
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < PW; ++s) {
-      int col = g + s * G;
-      if (col < w) Us[c * PW + col] = acc[s];
-    }
-  }
-  __syncthreads();
-}
-
-// acc[col] += sum_c P(row, c) Vs[c * PW + col] for this lane's row.
-__device__ __forceinline__ void expand_row(const double* __restrict__ P, int64_t rowidx, int ldp, int ptrans,
-                                           int k, const double* Vs, int w, double* acc) {
-  for (int c = 0; c < k; ++c) {
-    double p = ptrans ? P[c + rowidx * ldp] : P[rowidx + int64_t(c) * ldp];
-#pragma unroll
-    for (int col = 0; col < PW; ++col)
-      if (col < w) acc[col] += p * Vs[c * PW + col];
-  }
-}
-
-// Vs (k x w, ld PW) <- V (k x w column-major, ld k)
-__device__ __forceinline__ void stage_v(const double* __restrict__ V, int k, int w, double* Vs) {
-  for (int i = threadIdx.x; i < k * w; i += 64) {
-    int c = i % k, col = i / k;
-    Vs[c * PW + col] = V[i];
-  }
-  __syncthreads();
-}
-
-// ---------------------------------------------------------------- term reductions
-__global__ void __launch_bounds__(64) k_term_p1(const TermItem* __restrict__ items, const TDesc* __restrict__ td,
-                                               const TInfo* __restrict__ ti, TreeView tv, double* __restrict__ vbuf) {
-  __shared__ double Us[64 * PW];
-  const TermItem it = items[blockIdx.x];
-  const TDesc d = td[it.t];
-  if (d.w == 0) return;
-  const Term T = tv.terms[it.term];
-  const int tb = ti[it.t].block;
-  const int tau = tv.b_tau[tb], sig = tv.b_sigma[tb];
-  const double* M;
-  int ldm, mtrans, rows, k, kout, mode;
-  if (!d.trans) {  // V = core (R[sigma]^T X)
-    const int rr = tv.c_begin[sig] - T.rrow0;
-    M = T.rtrans ? T.R + int64_t(rr) * T.ldr : T.R + rr;
-    ldm = T.ldr;
-    mtrans = T.rtrans;
-    rows = tv.c_size[sig];
-    k = T.kr;
-    kout = T.kl;
-    mode = T.core ? 1 : 0;
-  } else {  // V = core^T (L[tau]^T X)
-    M = T.L + (tv.c_begin[tau] - T.lrow0);
-    ldm = T.ldl;
-    mtrans = 0;
-    rows = tv.c_size[tau];
-    k = T.kl;
-    kout = T.kr;
-    mode = T.core ? 2 : 0;
-  }
-  if (k == 0 || kout == 0) return;
-  reduce_wave(M, ldm, mtrans, rows, k, d.X, d.ldx, d.xident, d.xcol0, d.w, Us);
-  double* V = vbuf + it.voff;
-  for (int p = threadIdx.x; p < kout * d.w; p += 64) {
-    int i = p % kout, col = p / kout;
-    double v;
-    if (mode == 0) {
-      v = Us[i * PW + col];
-    } else if (mode == 1) {
-      v = 0.0;
-      for (int c = 0; c < T.kr; ++c) v += T.core[i + int64_t(c) * T.kl] * Us[c * PW + col];
-    } else {
-      v = 0.0;
-      for (int c = 0; c < T.kl; ++c) v += T.core[c + int64_t(i) * T.kl] * Us[c * PW + col];
-    }
-    V[p] = v;
-  }
-}
 
 // ---------------------------------------------------------------- subtree tasks
 __device__ __forceinline__ void task_input(const Task& tk, const TDesc* td, const double*& X, int& ldx, int& w,
@@ -167,52 +50,238 @@ __device__ __forceinline__ void task_input(const Task& tk, const TDesc* td, cons
   }
 }
 
-__global__ void __launch_bounds__(64) k_leaf_p1(const LeafItem* __restrict__ items, const Task* __restrict__ tasks,
-                                               const TDesc* __restrict__ td, TreeView tv, MatView ma, MatView mb,
-                                               double* __restrict__ ws) {
-  __shared__ double Us[64 * PW];
-  const LeafItem it = items[blockIdx.x];
-  const Task tk = tasks[it.task];
+// ---------------------------------------------------------------- fused small targets
+// One wave applies a whole target whose input and output clusters have at most
+// 64 rows: for every low-rank term of every ancestor, U = M^T X (M = R forward,
+// L transposed), V = core U (or core^T U), Y += P V (P = L forward, R transposed),
+// all on v_mfma_f64_16x16x4f64. Operand layouts on gfx950: A[i][k] at lane i + 16k,
+// B[k][j] at lane j + 16k, and accumulator register v of lane l holds D[l/16 + 4v][l%16]
+// -- so accumulator register v is exactly the B operand of K-step v of the next product.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ dbl4 mfma4(double a, double b, dbl4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__global__ void __launch_bounds__(64) k_fused_terms(const int32_t* __restrict__ tlist, const TDesc* __restrict__ td,
+                                                   const TInfo* __restrict__ ti, const HPair* __restrict__ hp,
+                                                   TreeView tv) {
+  const int t = tlist[blockIdx.x];
+  const TDesc d = td[t];
+  if (d.w == 0) return;
+  const int lane = threadIdx.x;
+  const int li = lane & 15, lk = lane >> 4;
+  const TInfo inf = ti[t];
+  const int tb = inf.block;
+  const int tau = tv.b_tau[tb], sig = tv.b_sigma[tb];
+  const int outc = d.trans ? sig : tau, inc = d.trans ? tau : sig;
+  const int nout = tv.c_size[outc], nin = tv.c_size[inc];
+  const int out0 = tv.c_begin[outc], in0 = tv.c_begin[inc];
+  const int w = d.w;
+  const int ksteps = (nin + 3) >> 2;  // K-steps over the input rows
+  const int ntile = (nout + 15) >> 4;
+  // X as B operands: xb[s] = X(4s + lk, li)
+  double xb[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int r = 4 * s + lk;
+    double v = 0.0;
+    if (r < nin && li < w) v = d.xident ? (r == d.xcol0 + li ? 1.0 : 0.0) : d.X[r + int64_t(li) * d.ldx];
+    xb[s] = v;
+  }
+  dbl4 y[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) y[q] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int a = tb; a >= 0; a = tv.b_parent[a]) {
+    for (int it = tv.group_ptr[a]; it < tv.group_ptr[a + 1]; ++it) {
+      const Term T = tv.terms[it];
+      // reduction operand M (rows = input cluster), expansion operand P (rows = output cluster)
+      const double* M;
+      int ldm, mtr, kin;
+      const double* P;
+      int ldp, ptr, kp;
+      if (!d.trans) {
+        const int rr = in0 - T.rrow0;
+        M = T.rtrans ? T.R + int64_t(rr) * T.ldr : T.R + rr;
+        ldm = T.ldr;
+        mtr = T.rtrans;
+        kin = T.kr;
+        P = T.L + (out0 - T.lrow0);
+        ldp = T.ldl;
+        ptr = 0;
+        kp = T.kl;
+      } else {
+        M = T.L + (in0 - T.lrow0);
+        ldm = T.ldl;
+        mtr = 0;
+        kin = T.kl;
+        const int rr = out0 - T.rrow0;
+        P = T.rtrans ? T.R + int64_t(rr) * T.ldr : T.R + rr;
+        ldp = T.ldr;
+        ptr = T.rtrans;
+        kp = T.kr;
+      }
+      const int nkb = (kin + 15) >> 4;
+      dbl4 U[4];
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) {
+        U[kb] = dbl4{0.0, 0.0, 0.0, 0.0};
+        if (kb < nkb) {
+          const int c = 16 * kb + li;
+#pragma unroll
+          for (int s = 0; s < 16; ++s) {
+            if (s < ksteps) {
+              const int r = 4 * s + lk;
+              double av = 0.0;
+              if (c < kin && r < nin) av = mtr ? M[c + int64_t(r) * ldm] : M[r + int64_t(c) * ldm];
+              U[kb] = mfma4(av, xb[s], U[kb]);
+            }
+          }
+        }
+      }
+      dbl4 V[4];
+      int nob;
+      if (T.core) {
+        nob = (kp + 15) >> 4;
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+          V[ob] = dbl4{0.0, 0.0, 0.0, 0.0};
+          if (ob < nob) {
+            const int i = 16 * ob + li;
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+              if (kb < nkb) {
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) {
+                  const int cc = 16 * kb + 4 * s4 + lk;
+                  double av = 0.0;
+                  if (i < kp && cc < kin) av = d.trans ? T.core[cc + int64_t(i) * T.kl] : T.core[i + int64_t(cc) * T.kl];
+                  V[ob] = mfma4(av, U[kb][s4], V[ob]);
+                }
+              }
+            }
+          }
+        }
+      } else {
+        nob = nkb;
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) V[ob] = U[ob];
+      }
+#pragma unroll
+      for (int tile = 0; tile < 4; ++tile) {
+        if (tile < ntile) {
+          const int row = 16 * tile + li;
+#pragma unroll
+          for (int ob = 0; ob < 4; ++ob) {
+            if (ob < nob) {
+#pragma unroll
+              for (int s4 = 0; s4 < 4; ++s4) {
+                const int cc = 16 * ob + 4 * s4 + lk;
+                double av = 0.0;
+                if (cc < kp && row < nout) av = ptr ? P[cc + int64_t(row) * ldp] : P[row + int64_t(cc) * ldp];
+                y[tile] = mfma4(av, V[ob][s4], y[tile]);
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  // pair results and output: y[tile][v] = Y(16 tile + lk + 4v, li)
+#pragma unroll
+  for (int tile = 0; tile < 4; ++tile) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * tile + lk + 4 * v;
+      if (tile < ntile && row < nout && li < w) {
+        double val = y[tile][v];
+        for (int j = inf.hp_begin; j < inf.hp_end; ++j) val += hp[j].temp2[row + int64_t(li) * nout];
+        const int jo = li < d.split ? li : li + d.gap;
+        d.Y[row + int64_t(jo) * d.ldy] = val;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- subtree products on MFMA
+// Work items are enumerated on the device: item g belongs to the task k with
+// pre[k] <= g < pre[k+1] (binary search), and is the (g - pre[k])-th depth-first
+// leaf of the task's subtree (reduction) or leaf cluster of its output (expansion).
+__device__ __forceinline__ int find_owner(const int64_t* __restrict__ pre, int n, int64_t g) {
+  int lo = 0, hi = n;  // pre[lo] <= g < pre[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (pre[mid] <= g) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(64) k_leaf_reduce(const int64_t* __restrict__ pre, int ntask, int64_t g0,
+                                                   const Task* __restrict__ tasks, const TDesc* __restrict__ td,
+                                                   const int32_t* __restrict__ dfs_block, TreeView tv, MatView ma,
+                                                   MatView mb, double* __restrict__ ws) {
+  const int64_t g = g0 + blockIdx.x;
+  const int k = find_owner(pre, ntask, g);
+  const Task tk = tasks[k];
+  const int b = dfs_block[tk.lo + int(g - pre[k])];
+  if (tv.b_kind[b] != KIND_F) return;
+  const MatView& mv = tk.mat ? mb : ma;
+  const int kr = mv.rank[b];
+  if (kr == 0) return;
   const double* X;
   int ldx, w, xident, xc0;
   task_input(tk, td, X, ldx, w, xident, xc0);
   if (w == 0) return;
-  const MatView& mv = tk.mat ? mb : ma;
-  const int b = it.block;
-  const int k = mv.rank[b];
-  if (k == 0) return;
+  const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
   const int qt = tv.b_tau[tk.q], qs = tv.b_sigma[tk.q];
   const int bt = tv.b_tau[b], bs = tv.b_sigma[b];
   const int m = tv.c_size[bt], n = tv.c_size[bs];
   const double* base = mv.pool + mv.off[b];
   const double* M;
   int rows, ro, ldm;
-  if (!tk.trans) {  // T = R^T X[sigma_b]
-    M = base + int64_t(k) * m;
+  if (!tk.trans) {
+    M = base + int64_t(kr) * m;
     ldm = n;
     rows = n;
     ro = tv.c_begin[bs] - tv.c_begin[qs];
-  } else {  // T = L^T X[tau_b]
+  } else {
     M = base;
     ldm = m;
     rows = m;
     ro = tv.c_begin[bt] - tv.c_begin[qt];
   }
-  const double* Xr = xident ? X : X + ro;
-  reduce_wave(M, ldm, 0, rows, k, Xr, ldx, xident, xc0 - ro, w, Us);
+  const int nkb = (kr + 15) >> 4;
+  const int ks = (rows + 3) >> 2;
   double* T = ws + tk.tws + (mv.kpref[tv.b_dfs[b]] - mv.kpref[tk.lo]) * PW;
-  for (int p = threadIdx.x; p < k * w; p += 64) {
-    int i = p % k, col = p / k;
-    T[p] = Us[i * PW + col];
+  for (int kb = 0; kb < nkb; ++kb) {
+    dbl4 U = dbl4{0.0, 0.0, 0.0, 0.0};
+    const int c = 16 * kb + li;
+    for (int s = 0; s < ks; ++s) {
+      const int r = 4 * s + lk;
+      double av = 0.0, bv = 0.0;
+      if (r < rows) {
+        if (c < kr) av = M[r + int64_t(c) * ldm];
+        if (li < w) bv = xident ? ((ro + r) == xc0 + li ? 1.0 : 0.0) : X[(ro + r) + int64_t(li) * ldx];
+      }
+      U = mfma4(av, bv, U);
+    }
+    // U[v] = T(16 kb + lk + 4v, li); T is kr x w column-major
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * kb + lk + 4 * v;
+      if (i < kr && li < w) T[i + int64_t(li) * kr] = U[v];
+    }
   }
 }
 
-__global__ void __launch_bounds__(64) k_subtree_p2(const RowItem* __restrict__ items, const Task* __restrict__ tasks,
-                                                  const TDesc* __restrict__ td, TreeView tv, MatView ma, MatView mb,
-                                                  const double* __restrict__ ws) {
-  __shared__ double Vs[64 * PW];
-  const RowItem it = items[blockIdx.x];
-  const Task tk = tasks[it.owner];
+__global__ void __launch_bounds__(64) k_subtree_expand(const int64_t* __restrict__ pre, int ntask, int64_t g0,
+                                                      const Task* __restrict__ tasks, const TDesc* __restrict__ td,
+                                                      TreeView tv, MatView ma, MatView mb,
+                                                      const double* __restrict__ ws) {
+  const int64_t g = g0 + blockIdx.x;
+  const int kt = find_owner(pre, ntask, g);
+  const Task tk = tasks[kt];
   const double* X;
   int ldx, w, xident, xc0;
   task_input(tk, td, X, ldx, w, xident, xc0);
@@ -221,76 +290,186 @@ __global__ void __launch_bounds__(64) k_subtree_p2(const RowItem* __restrict__ i
   const int qt = tv.b_tau[tk.q], qs = tv.b_sigma[tk.q];
   const int outc = tk.trans ? qs : qt, inc = tk.trans ? qt : qs;
   const int in0 = tv.c_begin[inc], in1 = in0 + tv.c_size[inc];
-  const int c = tv.leaf_clusters[it.lc];
-  const int row_lo = tv.c_begin[c] + it.chunk * 64;
-  const int nr = min(64, tv.c_begin[c] + tv.c_size[c] - row_lo);
-  const int lane = threadIdx.x;
-  const bool rok = lane < nr;
-  const int row = row_lo + (rok ? lane : 0);
-  double acc[PW];
+  const int c = tv.leaf_clusters[tv.c_lc_begin[outc] + int(g - pre[kt])];
+  const int row_lo = tv.c_begin[c];
+  const int nr = tv.c_size[c];  // leaf clusters have at most 64 rows
+  const int ntile = (nr + 15) >> 4;
+  const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+  dbl4 y[4];
 #pragma unroll
-  for (int s = 0; s < PW; ++s) acc[s] = 0.0;
+  for (int q = 0; q < 4; ++q) y[q] = dbl4{0.0, 0.0, 0.0, 0.0};
   for (int a = c; a >= 0; a = tv.c_parent[a]) {
-    const int p0 = tk.trans ? tv.bcol_ptr[a] : tv.brow_ptr[a];
+    const int* lst = tk.trans ? tv.bcol_blk : tv.brow_blk;
+    int p0 = tk.trans ? tv.bcol_ptr[a] : tv.brow_ptr[a];
     const int p1 = tk.trans ? tv.bcol_ptr[a + 1] : tv.brow_ptr[a + 1];
+    {  // the list is sorted by the first position of the other cluster: skip to in0
+      int lo = p0, hi = p1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const int bm = lst[mid];
+        if (tv.c_begin[tk.trans ? tv.b_tau[bm] : tv.b_sigma[bm]] < in0) lo = mid + 1;
+        else hi = mid;
+      }
+      p0 = lo;
+    }
     for (int p = p0; p < p1; ++p) {
-      const int b = tk.trans ? tv.bcol_blk[p] : tv.brow_blk[p];
+      const int b = lst[p];
       const int oth = tk.trans ? tv.b_tau[b] : tv.b_sigma[b];
       const int o0 = tv.c_begin[oth], o1 = o0 + tv.c_size[oth];
-      if (o0 < in0 || o1 > in1) continue;
-      const int bt = tv.b_tau[b], bs = tv.b_sigma[b];
-      const int m = tv.c_size[bt], n = tv.c_size[bs];
+      if (o0 >= in1) break;
+      if (o1 > in1) continue;
+      const int m = tv.c_size[tv.b_tau[b]], n = tv.c_size[tv.b_sigma[b]];
       const double* base = mv.pool + mv.off[b];
-      const int64_t ridx = row - tv.c_begin[a];
+      const int roff = row_lo - tv.c_begin[a];  // first output row inside the leaf's rows
       if (tv.b_kind[b] == KIND_F) {
         const int k = mv.rank[b];
         if (k == 0) continue;
-        const double* V = ws + tk.tws + (mv.kpref[tv.b_dfs[b]] - mv.kpref[tk.lo]) * PW;
-        stage_v(V, k, w, Vs);
-        if (rok) {
-          if (!tk.trans) expand_row(base, ridx, m, 0, k, Vs, w, acc);
-          else expand_row(base + int64_t(k) * m, ridx, n, 0, k, Vs, w, acc);
-        }
-        __syncthreads();
-      } else {
-        // dense leaf: stream its input rows through LDS in chunks of 64
-        const int nin = tk.trans ? m : n;
-        const int xo = o0 - in0;
-        for (int j0 = 0; j0 < nin; j0 += 64) {
-          const int jn = min(64, nin - j0);
-          for (int i = lane; i < jn * w; i += 64) {
-            int j = i % jn, col = i / jn;
-            int r = xo + j0 + j;
-            Vs[j * PW + col] = xident ? (r == xc0 + col ? 1.0 : 0.0) : X[r + int64_t(col) * ldx];
-          }
-          __syncthreads();
-          if (rok) {
-            for (int j = 0; j < jn; ++j) {
-              double dv = tk.trans ? base[(j0 + j) + ridx * m] : base[ridx + int64_t(j0 + j) * m];
+        const double* Tm = ws + tk.tws + (mv.kpref[tv.b_dfs[b]] - mv.kpref[tk.lo]) * PW;
+        const double* P = tk.trans ? base + int64_t(k) * m : base;
+        const int ldp = tk.trans ? n : m;
+        const int ks = (k + 3) >> 2;
+        for (int s = 0; s < ks; ++s) {
+          const int cc = 4 * s + lk;
+          const double bv = (cc < k && li < w) ? Tm[cc + int64_t(li) * k] : 0.0;
 #pragma unroll
-              for (int col = 0; col < PW; ++col)
-                if (col < w) acc[col] += dv * Vs[j * PW + col];
+          for (int tile = 0; tile < 4; ++tile) {
+            if (tile < ntile) {
+              const int r = 16 * tile + li;
+              const double av = (cc < k && r < nr) ? P[(roff + r) + int64_t(cc) * ldp] : 0.0;
+              y[tile] = mfma4(av, bv, y[tile]);
             }
           }
-          __syncthreads();
+        }
+      } else {
+        const int nin = tk.trans ? m : n;
+        const int xo = o0 - in0;
+        const int ks = (nin + 3) >> 2;
+        for (int s = 0; s < ks; ++s) {
+          const int j = 4 * s + lk;
+          double bv = 0.0;
+          if (j < nin && li < w)
+            bv = xident ? ((xo + j) == xc0 + li ? 1.0 : 0.0) : X[(xo + j) + int64_t(li) * ldx];
+#pragma unroll
+          for (int tile = 0; tile < 4; ++tile) {
+            if (tile < ntile) {
+              const int r = 16 * tile + li;
+              double av = 0.0;
+              if (j < nin && r < nr)
+                av = tk.trans ? base[j + int64_t(roff + r) * m] : base[(roff + r) + int64_t(j) * m];
+              y[tile] = mfma4(av, bv, y[tile]);
+            }
+          }
         }
       }
     }
     if (a == outc) break;
   }
-  if (rok) {
-    const int64_t orow = row - tv.c_begin[outc];
+  const int orow0 = row_lo - tv.c_begin[outc];
 #pragma unroll
-    for (int col = 0; col < PW; ++col)
-      if (col < w) tk.Y[orow + int64_t(col) * tk.ldy] = acc[col];
+  for (int tile = 0; tile < 4; ++tile) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * tile + lk + 4 * v;
+      if (tile < ntile && r < nr && li < w) tk.Y[(orow0 + r) + int64_t(li) * tk.ldy] = y[tile][v];
+    }
   }
 }
 
-// ---------------------------------------------------------------- target gather
-__global__ void __launch_bounds__(64) k_gather(const RowItem* __restrict__ items, const TDesc* __restrict__ td,
-                                              const TInfo* __restrict__ ti, const HPair* __restrict__ hp, TreeView tv,
-                                              const double* __restrict__ vbuf) {
-  __shared__ double Vs[64 * PW];
+// Large targets: per (target, term) V = core (M^T X) on MFMA (M = R forward, L
+// transposed), written to the target's slot; the expansion is k_gather_mfma.
+__global__ void __launch_bounds__(64) k_term_reduce(const TermItem* __restrict__ items, const TDesc* __restrict__ td,
+                                                   const TInfo* __restrict__ ti, TreeView tv,
+                                                   double* __restrict__ vbuf) {
+  const TermItem it = items[blockIdx.x];
+  const TDesc d = td[it.t];
+  if (d.w == 0) return;
+  const Term T = tv.terms[it.term];
+  const int tb = ti[it.t].block;
+  const int tau = tv.b_tau[tb], sig = tv.b_sigma[tb];
+  const double* M;
+  int ldm, mtr, nin, kin, kout;
+  if (!d.trans) {
+    const int rr = tv.c_begin[sig] - T.rrow0;
+    M = T.rtrans ? T.R + int64_t(rr) * T.ldr : T.R + rr;
+    ldm = T.ldr;
+    mtr = T.rtrans;
+    nin = tv.c_size[sig];
+    kin = T.kr;
+    kout = T.kl;
+  } else {
+    M = T.L + (tv.c_begin[tau] - T.lrow0);
+    ldm = T.ldl;
+    mtr = 0;
+    nin = tv.c_size[tau];
+    kin = T.kl;
+    kout = T.kr;
+  }
+  if (kin == 0 || kout == 0) return;
+  const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+  const int w = d.w;
+  const int nkb = (kin + 15) >> 4;
+  const int ks = (nin + 3) >> 2;
+  dbl4 U[4];
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) U[kb] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int s = 0; s < ks; ++s) {
+    const int r = 4 * s + lk;
+    double bv = 0.0;
+    if (r < nin && li < w) bv = d.xident ? (r == d.xcol0 + li ? 1.0 : 0.0) : d.X[r + int64_t(li) * d.ldx];
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      if (kb < nkb) {
+        const int c = 16 * kb + li;
+        double av = 0.0;
+        if (c < kin && r < nin) av = mtr ? M[c + int64_t(r) * ldm] : M[r + int64_t(c) * ldm];
+        U[kb] = mfma4(av, bv, U[kb]);
+      }
+    }
+  }
+  double* V = vbuf + it.voff;  // kout x w, column-major
+  if (T.core) {
+    const int nob = (kout + 15) >> 4;
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+      if (ob < nob) {
+        dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+        const int i = 16 * ob + li;
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+          if (kb < nkb) {
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+              const int cc = 16 * kb + 4 * s4 + lk;
+              double av = 0.0;
+              if (i < kout && cc < kin) av = d.trans ? T.core[cc + int64_t(i) * T.kl] : T.core[i + int64_t(cc) * T.kl];
+              acc = mfma4(av, U[kb][s4], acc);
+            }
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * ob + lk + 4 * v;
+          if (row < kout && li < w) V[row + int64_t(li) * kout] = acc[v];
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      if (kb < nkb) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * kb + lk + 4 * v;
+          if (row < kout && li < w) V[row + int64_t(li) * kout] = U[kb][v];
+        }
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(64) k_gather_mfma(const RowItem* __restrict__ items, const TDesc* __restrict__ td,
+                                                   const TInfo* __restrict__ ti, const HPair* __restrict__ hp,
+                                                   TreeView tv, const double* __restrict__ vbuf) {
   const RowItem it = items[blockIdx.x];
   const TDesc d = td[it.owner];
   if (d.w == 0) return;
@@ -298,15 +477,14 @@ __global__ void __launch_bounds__(64) k_gather(const RowItem* __restrict__ items
   const int tb = inf.block;
   const int outc = d.trans ? tv.b_sigma[tb] : tv.b_tau[tb];
   const int c = tv.leaf_clusters[it.lc];
-  const int row_lo = tv.c_begin[c] + it.chunk * 64;
-  const int nr = min(64, tv.c_begin[c] + tv.c_size[c] - row_lo);
-  const int lane = threadIdx.x;
-  const bool rok = lane < nr;
-  const int row = row_lo + (rok ? lane : 0);
+  const int row_lo = tv.c_begin[c];
+  const int nr = tv.c_size[c];
+  const int ntile = (nr + 15) >> 4;
+  const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
   const int w = d.w;
-  double acc[PW];
+  dbl4 y[4];
 #pragma unroll
-  for (int s = 0; s < PW; ++s) acc[s] = 0.0;
+  for (int q = 0; q < 4; ++q) y[q] = dbl4{0.0, 0.0, 0.0, 0.0};
   int64_t voff = inf.vbase;
   for (int a = tb; a >= 0; a = tv.b_parent[a]) {
     for (int i = tv.group_ptr[a]; i < tv.group_ptr[a + 1]; ++i) {
@@ -315,78 +493,296 @@ __global__ void __launch_bounds__(64) k_gather(const RowItem* __restrict__ items
       const double* V = vbuf + voff;
       voff += int64_t(T.kl > T.kr ? T.kl : T.kr) * PW;
       if (kout == 0) continue;
-      stage_v(V, kout, w, Vs);
-      if (rok) {
-        if (!d.trans) expand_row(T.L, row - T.lrow0, T.ldl, 0, kout, Vs, w, acc);
-        else expand_row(T.R, row - T.rrow0, T.ldr, T.rtrans, kout, Vs, w, acc);
+      const double* P;
+      int ldp, ptr;
+      int64_t r0;
+      if (!d.trans) {
+        P = T.L;
+        ldp = T.ldl;
+        ptr = 0;
+        r0 = row_lo - T.lrow0;
+      } else {
+        P = T.R;
+        ldp = T.ldr;
+        ptr = T.rtrans;
+        r0 = row_lo - T.rrow0;
+      }
+      const int ks = (kout + 3) >> 2;
+      for (int s = 0; s < ks; ++s) {
+        const int cc = 4 * s + lk;
+        const double bv = (cc < kout && li < w) ? V[cc + int64_t(li) * kout] : 0.0;
+#pragma unroll
+        for (int tile = 0; tile < 4; ++tile) {
+          if (tile < ntile) {
+            const int r = 16 * tile + li;
+            double av = 0.0;
+            if (cc < kout && r < nr) av = ptr ? P[cc + (r0 + r) * ldp] : P[(r0 + r) + int64_t(cc) * ldp];
+            y[tile] = mfma4(av, bv, y[tile]);
+          }
+        }
+      }
+    }
+  }
+  const int orow0 = row_lo - tv.c_begin[outc];
+  const int ld2 = tv.c_size[outc];
+#pragma unroll
+  for (int tile = 0; tile < 4; ++tile) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * tile + lk + 4 * v;
+      if (tile < ntile && r < nr && li < w) {
+        const int64_t orow = orow0 + r;
+        double val = y[tile][v];
+        for (int j = inf.hp_begin; j < inf.hp_end; ++j) val += hp[j].temp2[orow + int64_t(li) * ld2];
+        const int jo = li < d.split ? li : li + d.gap;
+        d.Y[orow + int64_t(jo) * d.ldy] = val;
+      }
+    }
+  }
+}
+
+void launch_term_reduce(const TermItem* items, size_t n, const TDesc* td, const TInfo* ti, const TreeView& tv,
+                        double* vbuf, hipStream_t s) {
+  const size_t maxg = size_t(1) << 30;
+  for (size_t b = 0; b < n; b += maxg) {
+    unsigned cnt = unsigned(std::min(maxg, n - b));
+    hipLaunchKernelGGL(k_term_reduce, dim3(cnt), dim3(64), 0, s, items + b, td, ti, tv, vbuf);
+    HM_CHECK_HIP(hipGetLastError());
+  }
+}
+
+void launch_gather_mfma(const RowItem* items, size_t n, const TDesc* td, const TInfo* ti, const HPair* hp,
+                        const TreeView& tv, const double* vbuf, hipStream_t s) {
+  const size_t maxg = size_t(1) << 30;
+  for (size_t b = 0; b < n; b += maxg) {
+    unsigned cnt = unsigned(std::min(maxg, n - b));
+    hipLaunchKernelGGL(k_gather_mfma, dim3(cnt), dim3(64), 0, s, items + b, td, ti, hp, tv, vbuf);
+    HM_CHECK_HIP(hipGetLastError());
+  }
+}
+
+void launch_leaf_reduce(const int64_t* pre, int ntask, int64_t nitems, const Task* tasks, const TDesc* td,
+                        const int32_t* dfs_block, const TreeView& tv, const MatView& ma, const MatView& mb,
+                        double* ws, hipStream_t s) {
+  const int64_t maxg = int64_t(1) << 30;
+  for (int64_t b = 0; b < nitems; b += maxg) {
+    unsigned cnt = unsigned(std::min(maxg, nitems - b));
+    hipLaunchKernelGGL(k_leaf_reduce, dim3(cnt), dim3(64), 0, s, pre, ntask, b, tasks, td, dfs_block, tv, ma, mb,
+                       ws);
+    HM_CHECK_HIP(hipGetLastError());
+  }
+}
+
+void launch_subtree_expand(const int64_t* pre, int ntask, int64_t nitems, const Task* tasks, const TDesc* td,
+                           const TreeView& tv, const MatView& ma, const MatView& mb, const double* ws,
+                           hipStream_t s) {
+  const int64_t maxg = int64_t(1) << 30;
+  for (int64_t b = 0; b < nitems; b += maxg) {
+    unsigned cnt = unsigned(std::min(maxg, nitems - b));
+    hipLaunchKernelGGL(k_subtree_expand, dim3(cnt), dim3(64), 0, s, pre, ntask, b, tasks, td, tv, ma, mb, ws);
+    HM_CHECK_HIP(hipGetLastError());
+  }
+}
+
+// Four waves per target for clusters of up to 256 rows: wave q reduces input rows
+// [64q, 64q + 64) and expands output rows [64q, 64q + 64); the partial products
+// M^T X of the four waves are summed through double-buffered LDS (one barrier per term).
+__global__ void __launch_bounds__(256) k_fused_terms4(const int32_t* __restrict__ tlist, const TDesc* __restrict__ td,
+                                                     const TInfo* __restrict__ ti, const HPair* __restrict__ hp,
+                                                     TreeView tv) {
+  __shared__ double ulds[2][4][4][4][64];  // buffer, wave, k-block, register, lane
+  const int t = tlist[blockIdx.x];
+  const TDesc d = td[t];
+  if (d.w == 0) return;
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const TInfo inf = ti[t];
+  const int tb = inf.block;
+  const int tau = tv.b_tau[tb], sig = tv.b_sigma[tb];
+  const int outc = d.trans ? sig : tau, inc = d.trans ? tau : sig;
+  const int nout = tv.c_size[outc], nin = tv.c_size[inc];
+  const int out0 = tv.c_begin[outc], in0 = tv.c_begin[inc];
+  const int w = d.w;
+  const int rin0 = 64 * wid, rout0 = 64 * wid;  // this wave's input / output row offset
+  const int nin_w = max(0, min(64, nin - rin0)), nout_w = max(0, min(64, nout - rout0));
+  const int ksteps = (nin_w + 3) >> 2;
+  const int ntile = (nout_w + 15) >> 4;
+  double xb[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int r = 4 * s + lk;
+    double v = 0.0;
+    if (r < nin_w && li < w) {
+      const int rr = rin0 + r;
+      v = d.xident ? (rr == d.xcol0 + li ? 1.0 : 0.0) : d.X[rr + int64_t(li) * d.ldx];
+    }
+    xb[s] = v;
+  }
+  dbl4 y[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) y[q] = dbl4{0.0, 0.0, 0.0, 0.0};
+  int buf = 0;
+  for (int a = tb; a >= 0; a = tv.b_parent[a]) {
+    for (int it = tv.group_ptr[a]; it < tv.group_ptr[a + 1]; ++it) {
+      const Term T = tv.terms[it];
+      const double* M;
+      int ldm, mtr, kin;
+      const double* P;
+      int ldp, ptr, kp;
+      if (!d.trans) {
+        const int rr = in0 - T.rrow0;
+        M = T.rtrans ? T.R + int64_t(rr) * T.ldr : T.R + rr;
+        ldm = T.ldr;
+        mtr = T.rtrans;
+        kin = T.kr;
+        P = T.L + (out0 - T.lrow0);
+        ldp = T.ldl;
+        ptr = 0;
+        kp = T.kl;
+      } else {
+        M = T.L + (in0 - T.lrow0);
+        ldm = T.ldl;
+        mtr = 0;
+        kin = T.kl;
+        const int rr = out0 - T.rrow0;
+        P = T.rtrans ? T.R + int64_t(rr) * T.ldr : T.R + rr;
+        ldp = T.ldr;
+        ptr = T.rtrans;
+        kp = T.kr;
+      }
+      const int nkb = (kin + 15) >> 4;
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) {
+        if (kb < nkb) {
+          dbl4 u = dbl4{0.0, 0.0, 0.0, 0.0};
+          const int c = 16 * kb + li;
+#pragma unroll
+          for (int s = 0; s < 16; ++s) {
+            if (s < ksteps) {
+              const int r = rin0 + 4 * s + lk;
+              double av = 0.0;
+              if (c < kin && 4 * s + lk < nin_w) av = mtr ? M[c + int64_t(r) * ldm] : M[r + int64_t(c) * ldm];
+              u = mfma4(av, xb[s], u);
+            }
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) ulds[buf][wid][kb][v][lane] = u[v];
+        }
       }
       __syncthreads();
-    }
-  }
-  const int64_t orow = row - tv.c_begin[outc];
-  const int ld2 = tv.c_size[outc];
-  if (rok) {
-    for (int j = inf.hp_begin; j < inf.hp_end; ++j) {
-      const double* T2 = hp[j].temp2;
+      dbl4 U[4];
 #pragma unroll
-      for (int col = 0; col < PW; ++col)
-        if (col < w) acc[col] += T2[orow + int64_t(col) * ld2];
-    }
+      for (int kb = 0; kb < 4; ++kb) {
+        U[kb] = dbl4{0.0, 0.0, 0.0, 0.0};
+        if (kb < nkb) {
 #pragma unroll
-    for (int col = 0; col < PW; ++col)
-      if (col < w) {
-        int jo = col < d.split ? col : col + d.gap;
-        d.Y[orow + int64_t(jo) * d.ldy] = acc[col];
+          for (int v = 0; v < 4; ++v)
+            U[kb][v] = ulds[buf][0][kb][v][lane] + ulds[buf][1][kb][v][lane] + ulds[buf][2][kb][v][lane] +
+                       ulds[buf][3][kb][v][lane];
+        }
       }
+      buf ^= 1;
+      dbl4 V[4];
+      int nob;
+      if (T.core) {
+        nob = (kp + 15) >> 4;
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+          V[ob] = dbl4{0.0, 0.0, 0.0, 0.0};
+          if (ob < nob) {
+            const int i = 16 * ob + li;
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+              if (kb < nkb) {
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) {
+                  const int cc = 16 * kb + 4 * s4 + lk;
+                  double av = 0.0;
+                  if (i < kp && cc < kin) av = d.trans ? T.core[cc + int64_t(i) * T.kl] : T.core[i + int64_t(cc) * T.kl];
+                  V[ob] = mfma4(av, U[kb][s4], V[ob]);
+                }
+              }
+            }
+          }
+        }
+      } else {
+        nob = nkb;
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) V[ob] = U[ob];
+      }
+#pragma unroll
+      for (int tile = 0; tile < 4; ++tile) {
+        if (tile < ntile) {
+          const int r = 16 * tile + li;
+#pragma unroll
+          for (int ob = 0; ob < 4; ++ob) {
+            if (ob < nob) {
+#pragma unroll
+              for (int s4 = 0; s4 < 4; ++s4) {
+                const int cc = 16 * ob + 4 * s4 + lk;
+                double av = 0.0;
+                if (cc < kp && r < nout_w) {
+                  const int row = rout0 + r;
+                  av = ptr ? P[cc + int64_t(row) * ldp] : P[row + int64_t(cc) * ldp];
+                }
+                y[tile] = mfma4(av, V[ob][s4], y[tile]);
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int tile = 0; tile < 4; ++tile) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * tile + lk + 4 * v;
+      if (tile < ntile && r < nout_w && li < w) {
+        const int row = rout0 + r;
+        double val = y[tile][v];
+        for (int j = inf.hp_begin; j < inf.hp_end; ++j) val += hp[j].temp2[row + int64_t(li) * nout];
+        const int jo = li < d.split ? li : li + d.gap;
+        d.Y[row + int64_t(jo) * d.ldy] = val;
+      }
+    }
   }
 }
 
-// ---------------------------------------------------------------- launch wrappers
-template <class ItemT>
-static void launch_items(void (*kern)(const ItemT*, const Task*, const TDesc*, TreeView, MatView, MatView, double*),
-                         const ItemT* items, size_t n, const Task* tasks, const TDesc* td, const TreeView& tv,
-                         const MatView& ma, const MatView& mb, double* ws, hipStream_t s) {
+void launch_fused_terms4(const int32_t* tlist, size_t n, const TDesc* td, const TInfo* ti, const HPair* hp,
+                         const TreeView& tv, hipStream_t s) {
   const size_t maxg = size_t(1) << 30;
   for (size_t b = 0; b < n; b += maxg) {
     unsigned cnt = unsigned(std::min(maxg, n - b));
-    hipLaunchKernelGGL(kern, dim3(cnt), dim3(64), 0, s, items + b, tasks, td, tv, ma, mb, ws);
+    hipLaunchKernelGGL(k_fused_terms4, dim3(cnt), dim3(256), 0, s, tlist + b, td, ti, hp, tv);
     HM_CHECK_HIP(hipGetLastError());
   }
 }
 
-void launch_leaf_p1(const LeafItem* items, size_t n, const Task* tasks, const TDesc* td, const TreeView& tv,
-                    const MatView& ma, const MatView& mb, double* ws, hipStream_t s) {
-  if (n) launch_items(k_leaf_p1, items, n, tasks, td, tv, ma, mb, ws, s);
-}
-
-void launch_subtree_p2(const RowItem* items, size_t n, const Task* tasks, const TDesc* td, const TreeView& tv,
-                       const MatView& ma, const MatView& mb, const double* ws, hipStream_t s) {
+void launch_fused_terms(const int32_t* tlist, size_t n, const TDesc* td, const TInfo* ti, const HPair* hp,
+                        const TreeView& tv, hipStream_t s) {
   const size_t maxg = size_t(1) << 30;
   for (size_t b = 0; b < n; b += maxg) {
     unsigned cnt = unsigned(std::min(maxg, n - b));
-    hipLaunchKernelGGL(k_subtree_p2, dim3(cnt), dim3(64), 0, s, items + b, tasks, td, tv, ma, mb, ws);
+    hipLaunchKernelGGL(k_fused_terms, dim3(cnt), dim3(64), 0, s, tlist + b, td, ti, hp, tv);
     HM_CHECK_HIP(hipGetLastError());
   }
 }
 
-void launch_term_p1(const TermItem* items, size_t n, const TDesc* td, const TInfo* ti, const TreeView& tv,
-                    double* vbuf, hipStream_t s) {
-  const size_t maxg = size_t(1) << 30;
-  for (size_t b = 0; b < n; b += maxg) {
-    unsigned cnt = unsigned(std::min(maxg, n - b));
-    hipLaunchKernelGGL(k_term_p1, dim3(cnt), dim3(64), 0, s, items + b, td, ti, tv, vbuf);
-    HM_CHECK_HIP(hipGetLastError());
-  }
+}  // namespace hm
+
+namespace hm {
+
+__global__ void k_scatter_terms(const int32_t* __restrict__ ids, const Term* __restrict__ src, Term* __restrict__ dst,
+                                int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) dst[ids[i]] = src[i];
 }
 
-void launch_gather(const RowItem* items, size_t n, const TDesc* td, const TInfo* ti, const HPair* hp,
-                   const TreeView& tv, const double* vbuf, hipStream_t s) {
-  const size_t maxg = size_t(1) << 30;
-  for (size_t b = 0; b < n; b += maxg) {
-    unsigned cnt = unsigned(std::min(maxg, n - b));
-    hipLaunchKernelGGL(k_gather, dim3(cnt), dim3(64), 0, s, items + b, td, ti, hp, tv, vbuf);
-    HM_CHECK_HIP(hipGetLastError());
-  }
+void launch_scatter_terms(const int32_t* ids, const Term* src, Term* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_scatter_terms, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, ids, src, dst, n);
+  HM_CHECK_HIP(hipGetLastError());
 }
 
 }  // namespace hm

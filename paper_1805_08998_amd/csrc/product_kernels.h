@@ -44,6 +44,7 @@ struct TreeView {
   const int32_t* bcol_blk;
   const int32_t* group_ptr;  // terms created at each block
   const Term* terms;
+  const int32_t* c_lc_begin;  // first index into leaf_clusters of each cluster
 };
 
 // Pass descriptor of one target: the target's operator is applied to X
