@@ -159,4 +159,8 @@ Opts resolve_opts(const hmat_opts* o);
 
 double now_seconds();
 
+// Rank predictor inference: feats holds HMAT_N_FEATURES floats per target; out receives
+// one predicted rank per target (synchronous on stream s).
+void predict_ranks(hmat_rank_model model, const std::vector<float>& feats, std::vector<float>& out, hipStream_t s);
+
 }  // namespace hm

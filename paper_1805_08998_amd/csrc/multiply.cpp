@@ -564,7 +564,35 @@ struct Chunk {
   std::vector<int32_t> small4;   // targets applied by the four-wave fused kernel
   std::vector<uint8_t> is_small;
   DevBuf<int32_t> d_small, d_small4;
+  std::vector<float> feats;  // HMAT_N_FEATURES per target (farfield chunks, when needed)
 };
+
+// Features of a farfield target for the rank predictor: level, log diam tau,
+// log diam sigma, log dist(tau, sigma), log(1 + sum of the ranks of the
+// sum-expression's terms, each H-pair counted by min(#rho, m, n)), number of
+// terms and pairs.
+void target_features(const Ctx& c, int32_t b, float* f) {
+  const Tree& t = *c.t;
+  const int32_t tau = t.b_tau[b], sig = t.b_sigma[b];
+  const int32_t m = t.c_size[tau], n = t.c_size[sig];
+  double rsum = 0;
+  int cnt = 0;
+  for (int32_t a = b; a >= 0; a = t.b_parent[a])
+    for (int32_t j = c.group_ptr_h[a]; j < c.group_ptr_h[a + 1]; ++j) {
+      rsum += std::min(c.sym[j].kl, c.sym[j].kr);
+      ++cnt;
+    }
+  for (int32_t j = c.hptr[b]; j < c.hptr[b + 1]; ++j) {
+    rsum += std::min(t.c_size[c.hrho[3 * j]], std::min(m, n));
+    ++cnt;
+  }
+  f[0] = float(t.b_level[b]);
+  f[1] = float(std::log(std::max(t.c_diam[tau], 1e-12)));
+  f[2] = float(std::log(std::max(t.c_diam[sig], 1e-12)));
+  f[3] = float(std::log(std::max(cluster_dist(t, tau, sig), 1e-12)));
+  f[4] = float(std::log1p(rsum));
+  f[5] = float(cnt);
+}
 
 int64_t target_cost(const Ctx& c, int32_t b, bool far, const Opts& o, int cap) {
   const Tree& t = *c.t;
@@ -584,9 +612,13 @@ int64_t target_cost(const Ctx& c, int32_t b, bool far, const Opts& o, int cap) {
   return 8 * (v + pr + panels) + 512;
 }
 
-void build_chunk(const Ctx& c, Chunk& ch) {
+void build_chunk(const Ctx& c, Chunk& ch, bool features) {
   const Tree& t = *c.t;
   const int nt = int(ch.blocks.size());
+  if (features) {
+    ch.feats.resize(size_t(nt) * HMAT_N_FEATURES);
+    for (int i = 0; i < nt; ++i) target_features(c, ch.blocks[i], &ch.feats[size_t(i) * HMAT_N_FEATURES]);
+  }
   ch.info.resize(nt);
   for (int k = 0; k < 4; ++k)
     for (int d = 0; d < 2; ++d) ch.coef[k][d].assign(nt, Coef{});
@@ -963,6 +995,7 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
   for (int i = 0; i < nt; ++i) {
     CTarget& T = h[i];
     if (!T.done) c.st.n_not_converged++;
+    if (T.rounds > 0 && c.opts.o.rank_mode == HMAT_RANK_PREDICT) c.st.n_fallback++;
     out.blocks.push_back(T.block);
     out.ranks.push_back(T.k);
     out.offs.push_back(out.len);
@@ -1141,6 +1174,8 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   tree_retain(t);
   C->rank.assign(nb, 0);
   C->off.assign(nb, -1);
+  const bool predict = opts.o.rank_mode == HMAT_RANK_PREDICT;
+  const bool collect = !predict && opts.o.stats != nullptr;
   std::vector<int32_t> far_all, near_all;
   for (int32_t b : t->leaves) (t->b_kind[b] == KIND_F ? far_all : near_all).push_back(b);
   c.st.n_far = int64_t(far_all.size());
@@ -1183,15 +1218,15 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     for (auto& p : partition(near, false)) jobs.push_back(Job{false, std::move(p)});
     for (auto& p : partition(far, true)) jobs.push_back(Job{true, std::move(p)});
     c.st.t_host[2] += now_seconds() - tp;
-    auto build = [&c](std::unique_ptr<Chunk> ch) {
-      build_chunk(c, *ch);
+    auto build = [&c](std::unique_ptr<Chunk> ch, bool features) {
+      build_chunk(c, *ch, features);
       return ch;
     };
     std::future<std::unique_ptr<Chunk>> next;
     auto launch_build = [&](size_t k) {
       auto ch = std::make_unique<Chunk>();
       ch->blocks = jobs[k].blocks;
-      next = std::async(std::launch::async, build, std::move(ch));
+      next = std::async(std::launch::async, build, std::move(ch), jobs[k].far && (predict || collect));
     };
     if (!jobs.empty()) launch_build(0);
     for (size_t k = 0; k < jobs.size(); ++k) {
@@ -1209,8 +1244,26 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
         c.st.t_near += now_seconds() - tn;
       } else {
         std::vector<int32_t> w0(ch.blocks.size(), opts.o.b0);
+        if (predict) {
+          // learned initial widths: predicted rank plus oversampling, within the panel
+          // capacity (the residual check still grows the sketch where this is too small)
+          const double tq = now_seconds();
+          std::vector<float> pred;
+          predict_ranks(opts.o.rank_model, ch.feats, pred, s);
+          for (size_t i = 0; i < w0.size(); ++i) {
+            const int mn = std::min(c.m_of(ch.blocks[i]), c.n_of(ch.blocks[i]));
+            const double pr = std::isfinite(pred[i]) ? std::ceil(double(pred[i])) : double(opts.o.b0);
+            w0[i] = int32_t(std::clamp(pr + opts.o.p_l, 1.0, double(std::min(mn, 64 - opts.o.probes))));
+          }
+          c.st.t_predict += now_seconds() - tq;
+        }
         outs.emplace_back();
         compress_chunk(c, ch, w0, outs.back());
+        if (collect) {
+          const FarOut& fo = outs.back();
+          C->features.feats.insert(C->features.feats.end(), ch.feats.begin(), ch.feats.end());
+          for (int32_t k : fo.ranks) C->features.ranks.push_back(float(k));
+        }
       }
     }
   };

@@ -18,7 +18,9 @@ HMAT_ERR_DEVICE, HMAT_ERR_OOM, HMAT_ERR_INTERNAL = 4, 5, 6
 HMAT_FP64, HMAT_FP32_APPLY, HMAT_BF16_SKETCH = 0, 1, 2
 HMAT_RANK_ADAPTIVE, HMAT_RANK_PREDICT = 0, 1
 KERN_NAMES = ["term_reduce", "leaf_reduce", "subtree_expand", "gather", "compress", "fused_terms", "k6", "k7"]
-KERN_SYMBOLS = ["k_term_p1", "k_leaf_p1", "k_subtree_p2", "k_gather", "compress", "k_fused_terms", "", ""]
+# device kernels of each family (the fused family is k_fused_terms and k_fused_terms4)
+KERN_SYMBOLS = ["k_term_reduce", "k_leaf_reduce", "k_subtree_expand", "k_gather_mfma",
+                "k_orth_append+k_probe_residual+k_check+k_core+k_write_factors", "k_fused_terms*", "", ""]
 KERNELS = {"laplace_4pi": 0, "inv_dist": 1, "exp": 2}
 
 
