@@ -1,10 +1,15 @@
 """Benchmark of the H-matrix product C = A B on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sphere256k] [--mode plain|learned|mixed]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sphere256k] [--mode learned|plain|mixed]
 
 One step is one whole product hmat_multiply(A, B, eps): every farfield block
 compressed, every nearfield block evaluated, on inputs already resident in HBM.
-Tree construction and assembly happen before the timed region. Prints one JSON
+Tree construction and assembly happen before the timed region. In learned mode
+the rank predictor is trained first (also untimed) on the farfield ranks of
+plain products of other workloads (the 65536-point sphere and the
+262144-point ellipsoid), then every timed product starts each compression
+with the predicted width; the plain adaptive form is timed after it for
+comparison. Prints one JSON
 line with the throughput (effective GFLOP/s = minimum algorithmic flops of the
 method / wall time), the roofline position of the dominant kernel family
 (measured with HIP events inside the timed steps) and the CPU oracle's rate on
@@ -79,7 +84,7 @@ def cpu_baseline(H, tree, A, B, eps, flops_alg, seconds=20.0, max_rows=256, seed
             if cand.size == 0:
                 continue
             ent, tt = 0.0, 0.0
-            for i in rng.permutation(cand)[:4]:
+            for i in rng.permutation(cand)[:64]:
                 r0, r1, c0, c1 = la["r0"][i], la["r1"][i], la["c0"][i], la["c1"][i]
                 for j in sa.rows_needed(r0, r1):  # fetch the inputs first: only the oracle is timed
                     sa.leaf(j)
@@ -124,13 +129,65 @@ def cpu_baseline(H, tree, A, B, eps, flops_alg, seconds=20.0, max_rows=256, seed
     }
 
 
+def train_predictor(H, configs, names, epochs, cache=None):
+    """Rank predictor trained on the farfield ranks of plain products of other
+    workloads (untimed). Returns the model handle and a summary. With `cache`,
+    the training features are read from that .npz file when it exists (written
+    by an earlier run with the same option), else computed and saved there."""
+    feats, ranks = [], []
+    t0 = time.perf_counter()
+    if cache and os.path.exists(cache):
+        with np.load(cache) as z:
+            feats, ranks = [z["feats"]], [z["ranks"]]
+            names = [str(x) for x in z["names"]] if "names" in z.files else names
+        log(f"[bench] predictor data from {cache}: {len(ranks[0])} farfield blocks")
+    for name in (names if not feats else []):
+        wl = configs[name]
+        tr = H.hmat_build_tree(wl.points(), wl.leaf, wl.eta, wl.split)
+        A, _ = H.hmat_assemble(tr, wl.kernel_a.kind, wl.kernel_a.diag, wl.kernel_a.shift, wl.eps_in)
+        B = A if wl.same_ab else H.hmat_assemble(tr, wl.kernel_b.kind, wl.kernel_b.diag, wl.kernel_b.shift,
+                                                  wl.eps_in)[0]
+        st = H.hmat_stats()
+        o = H.hmat_opts_default()
+        o.stats = ctypes.pointer(st)
+        C, _ = H.hmat_multiply(A, B, wl.eps, o, allow_not_converged=True)
+        f, r = H.hmat_product_features(C)
+        feats.append(f)
+        ranks.append(r)
+        for h in ([A, C] if wl.same_ab else [A, B, C]):
+            H.hmat_destroy(h)
+        H.hmat_tree_destroy(tr)
+        log(f"[bench] predictor data: {name}: {len(r)} farfield blocks")
+    f = np.concatenate(feats)
+    r = np.concatenate(ranks)
+    if cache and not os.path.exists(cache):
+        np.savez(cache, feats=f, ranks=r, names=np.array(names))
+    model = H.hmat_rank_model_create(1)
+    t1 = time.perf_counter()
+    losses = H.hmat_rank_model_train(model, f, r, H.hmat_train_opts_default(epochs=epochs, batch=512, lr=2e-3))
+    t2 = time.perf_counter()
+    pred = H.hmat_rank_model_predict(model, f)
+    rmse = float(np.sqrt(np.mean((pred - r) ** 2)))
+    log(f"[bench] predictor trained on {len(r)} blocks in {t2 - t1:.1f}s (data {t1 - t0:.1f}s), "
+        f"loss {losses[0]:.4f} -> {losses[-1]:.4f}, rank rmse {rmse:.2f}")
+    return model, {"train_on": names, "samples": int(len(r)), "epochs": epochs, "train_seconds": t2 - t1,
+                   "rank_rmse_train": rmse, "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sphere256k")
-    ap.add_argument("--mode", default="plain", choices=["plain", "mixed"])
+    ap.add_argument("--mode", default="learned", choices=["learned", "plain", "mixed"])
+    ap.add_argument("--train-on", default="sphere64k,ellipsoid256k",
+                    help="workloads whose plain products provide the predictor's training data")
+    ap.add_argument("--train-epochs", type=int, default=30)
+    ap.add_argument("--features-cache", default=None,
+                    help=".npz file of predictor training features (read if present, else written)")
+    ap.add_argument("--compare-steps", type=int, default=1,
+                    help="timed plain products after the learned ones (learned mode only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
@@ -146,6 +203,11 @@ def main():
     from paper_1805_08998_amd import hmat as H
 
     w = CONFIGS[args.workload]
+    model = None
+    train_info = None
+    if args.mode == "learned":
+        model, train_info = train_predictor(H, CONFIGS, args.train_on.split(","), args.train_epochs,
+                                            args.features_cache)
     pts = w.points()
     t0 = time.perf_counter()
     tree = H.hmat_build_tree(pts, w.leaf, w.eta, w.split)
@@ -158,11 +220,14 @@ def main():
     t2 = time.perf_counter()
     log(f"[bench] assembly of A and B {t2 - t1:.2f}s")
 
-    def run(time_kernels):
+    def run(time_kernels, mode=args.mode):
         st = H.hmat_stats()
         o = H.hmat_opts_default()
-        if args.mode == "mixed":
+        if mode == "mixed":
             o.precision = H.HMAT_FP32_APPLY
+        if mode == "learned":
+            o.rank_mode = H.HMAT_RANK_PREDICT
+            o.rank_model = model
         o.time_kernels = 1 if time_kernels else 0
         o.stats = ctypes.pointer(st)
         ts = time.perf_counter()
@@ -175,27 +240,53 @@ def main():
         H.hmat_destroy(C)
         log(f"[bench] warmup {i}: {dt:.3f}s plan {st['t_plan']:.3f} restrict {st['t_restrict']:.3f} "
             f"near {st['t_near']:.3f} sketch {st['t_sketch']:.3f} project {st['t_project']:.3f} "
-            f"core {st['t_core']:.3f} growth rounds {st['n_growth_rounds']} not converged {st['n_not_converged']}")
+            f"core {st['t_core']:.3f} growth rounds {st['n_growth_rounds']} not converged {st['n_not_converged']} "
+            f"batches {st['n_batches']} grown {st['n_grown_blocks']} columns {st['sketch_columns']}")
 
     times, stats = [], []
     C = None
     for i in range(args.steps):
         if C is not None:
             H.hmat_destroy(C)
-        C, st, dt = run(True)
+        C, st, dt = run(False)
         times.append(dt)
         stats.append(st)
-        log(f"[bench] step {i}: {dt:.3f}s")
+        log(f"[bench] step {i}: {dt:.3f}s batches {st['n_batches']} restrict {st['t_restrict']:.3f} "
+            f"near {st['t_near']:.3f} sketch {st['t_sketch']:.3f} project {st['t_project']:.3f} "
+            f"grown {st['n_grown_blocks']} fallback {st['n_fallback']} columns {st['sketch_columns']}")
     t = sum(times) / len(times)
     st = stats[-1]
     flops = st["flops_alg"]
+    # one more product with every kernel launch bracketed by HIP events on the
+    # library's stream: per-family launch durations for the roofline (event
+    # records slow the product down, so this step is not part of `value`)
+    H.hmat_destroy(C)
+    C, kst, kdt = run(True)
+    log(f"[bench] instrumented step: {kdt:.3f}s")
+    plain = None
+    if args.mode == "learned" and args.compare_steps > 0:
+        H.hmat_destroy(C)
+        C = None
+        pt = []
+        for i in range(args.compare_steps):
+            if C is not None:
+                H.hmat_destroy(C)
+            C, pst, dt = run(False, "plain")
+            pt.append(dt)
+            log(f"[bench] plain step {i}: {dt:.3f}s batches {pst['n_batches']} grown {pst['n_grown_blocks']} "
+                f"columns {pst['sketch_columns']} sketch {pst['t_sketch']:.3f} project {pst['t_project']:.3f}")
+        tp = sum(pt) / len(pt)
+        plain = {"seconds_per_product": tp, "gflops_effective": pst["flops_alg"] / tp / 1e9,
+                 "steps": len(pt), "n_growth_rounds": pst["n_growth_rounds"],
+                 "n_grown_blocks": pst["n_grown_blocks"], "sketch_columns": pst["sketch_columns"],
+                 "learned_speedup": tp / t}
 
     # roofline of the dominant kernel family (largest summed launch time)
-    ktime = np.array(st["kern_time"])
-    kb = np.array(st["kern_bytes"])
-    kf = np.array(st["kern_flops"])
-    kl = np.array(st["kern_launches"])
-    cand = [0, 1, 2, 3, 5]
+    ktime = np.array(kst["kern_time"])
+    kb = np.array(kst["kern_bytes"])
+    kf = np.array(kst["kern_flops"])
+    kl = np.array(kst["kern_launches"])
+    cand = [0, 1, 2, 3, 5, 6]
     dom = cand[int(np.argmax(ktime[cand]))]
     avg = ktime[dom] / max(1, kl[dom])
     bytes_per_launch = kb[dom] / max(1, kl[dom])
@@ -209,6 +300,7 @@ def main():
         "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
         "traffic": None,
         "avg_launch_us": 1e6 * avg,
+        "instrumented_step_s": kdt,
         "launches": int(kl[dom]),
         "alg_bytes_per_launch": bytes_per_launch,
         "alg_flops_per_launch": kf[dom] / max(1, kl[dom]),
@@ -217,7 +309,7 @@ def main():
         "families": {H.KERN_NAMES[k]: {"time_s": ktime[k], "launches": int(kl[k]),
                                        "GB_s": (kb[k] / ktime[k] / 1e9) if ktime[k] > 0 else None,
                                        "TFLOP_s": (kf[k] / ktime[k] / 1e12) if ktime[k] > 0 else None}
-                     for k in range(6)},
+                     for k in range(7)},
     }
     cpu = None
     if not args.no_cpu_baseline:
@@ -236,13 +328,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.mode == "plain" else "f32+f64",
+        "dtype": "f32+f64" if args.mode == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "geometry": w.geometry, "jitter": w.jitter, "leaf": w.leaf,
                    "eta": w.eta, "split": "midpoint" if w.split == 0 else "median",
                    "kernels": [f"{w.kernel_a.kind}+{w.kernel_a.shift}I", f"{w.kernel_b.kind}+{w.kernel_b.shift}I"],
                    "eps": w.eps, "eps_in": w.eps_in, "mode": args.mode, "seconds_per_product": t,
-                   "alg_flops": flops, "alg_bytes": st["bytes_alg"]},
+                   "alg_flops": flops, "alg_bytes": st["bytes_alg"], "predictor": train_info,
+                   "plain": plain},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stats": {k: v for k, v in st.items() if k not in ("rank_hist",)},

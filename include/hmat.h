@@ -172,7 +172,8 @@ enum {
   HMAT_KERN_SUBTREE_EXPAND = 2,/* subtree products: L T and D X per output leaf cluster */
   HMAT_KERN_GATHER = 3,        /* per target: sum of L V over its terms and pair results */
   HMAT_KERN_COMPRESS = 4,      /* orthogonalisation, probe residual, core SVD, output */
-  HMAT_KERN_FUSED_TERMS = 5    /* fused term reduce + expand for small targets */
+  HMAT_KERN_FUSED_TERMS = 5,   /* fused term reduce + expand, targets of <= 64 rows/columns */
+  HMAT_KERN_FUSED_TERMS4 = 6   /* the same with four waves, targets of <= 256 rows/columns */
 };
 
 typedef struct {
@@ -182,7 +183,7 @@ typedef struct {
   int32_t growth;      /* columns added per growth round (default 8) */
   int32_t probes;      /* probe columns of the a-posteriori check (default 8) */
   int32_t max_growth;  /* growth rounds before HMAT_ERR_NOT_CONVERGED (default 6) */
-  int32_t p_l;         /* oversampling added to a predicted rank (default 3) */
+  int32_t p_l;         /* oversampling added to a predicted rank (default 2) */
   int32_t time_kernels;/* 1: time every kernel launch with HIP events into stats */
   double delta;        /* residual target: E <= delta * eps * ||S||_F (default 0.2) */
   uint64_t seed;       /* random stream of the sketches (default 0x5eed) */

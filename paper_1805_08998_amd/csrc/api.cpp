@@ -44,6 +44,13 @@ static const size_t kCacheLimit = size_t(64) << 30;
 
 void set_current_stream(hipStream_t s) { g_stream = s; }
 
+size_t dev_free_bytes() {
+  size_t fb = 0, tb = 0;
+  HM_CHECK_HIP(hipMemGetInfo(&fb, &tb));
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  return fb + g_cached_bytes;
+}
+
 static size_t round_size(size_t b) {
   if (b <= (size_t(1) << 20)) {
     size_t r = 256;
@@ -249,7 +256,7 @@ void hmat_opts_default(hmat_opts* o) {
   o->growth = 8;
   o->probes = 8;
   o->max_growth = 6;
-  o->p_l = 3;
+  o->p_l = 2;
   o->delta = 0.2;
   o->seed = 0x5eedull;
 }

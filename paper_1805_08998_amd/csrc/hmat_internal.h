@@ -40,6 +40,8 @@ void* dev_alloc(size_t bytes);
 void dev_free(void* p);
 // stream on which freed blocks may still be in use (set by every entry point that launches work)
 void set_current_stream(hipStream_t s);
+// device memory available to the library: free memory plus blocks held by its cache
+size_t dev_free_bytes();
 // Copies host memory to the device and waits; large copies go through a pinned
 // staging buffer (allocated with hipHostMalloc and kept for reuse).
 void host_to_device(void* dst, const void* src, size_t bytes, hipStream_t s);

@@ -57,21 +57,28 @@ __global__ void k_dense_bwd_x(const float* __restrict__ dY, int n, int no, const
   dX[idx] = acc;
 }
 
-// dW (no x ni) = dY^T X / scale, db (no) = sum over samples of dY / scale (fixed order)
-__global__ void k_dense_bwd_w(const float* __restrict__ dY, int n, int no, const float* __restrict__ X, int ni,
-                              float scale, float* __restrict__ dW, float* __restrict__ db) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+// dW (no x ni) = dY^T X * scale, db (no) = column sums of dY * scale: one wave per
+// output entry, lanes stride over the samples, fixed-order butterfly sum
+__global__ void __launch_bounds__(256) k_dense_bwd_w(const float* __restrict__ dY, int n, int no,
+                                                     const float* __restrict__ X, int ni, float scale,
+                                                     float* __restrict__ dW, float* __restrict__ db) {
+  const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int total = no * ni + no;
   if (idx >= total) return;
   float acc = 0.f;
   if (idx < no * ni) {
     const int o = idx / ni, k = idx % ni;
-    for (int r = 0; r < n; ++r) acc += dY[int64_t(r) * no + o] * X[int64_t(r) * ni + k];
-    dW[idx] = acc * scale;
+    for (int r = lane; r < n; r += 64) acc += dY[int64_t(r) * no + o] * X[int64_t(r) * ni + k];
   } else {
     const int o = idx - no * ni;
-    for (int r = 0; r < n; ++r) acc += dY[int64_t(r) * no + o];
-    db[o] = acc * scale;
+    for (int r = lane; r < n; r += 64) acc += dY[int64_t(r) * no + o];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) {
+    if (idx < no * ni) dW[idx] = acc * scale;
+    else db[idx - no * ni] = acc * scale;
   }
 }
 
@@ -117,6 +124,7 @@ __global__ void k_unscale(const float* __restrict__ out, int n, const float* __r
 }
 
 static unsigned nblk(int64_t n) { return unsigned((n + 255) / 256); }
+static unsigned wblk(int64_t n) { return unsigned((n + 3) / 4); }  // one wave per item, 4 per block
 
 // ---------------------------------------------------------------- host helpers
 struct Work {
@@ -157,19 +165,19 @@ static void backward(RankModel& M, Work& W, const float* ranks, int n, hipStream
   float* G = M.g.p;
   const float sc = 1.f / float(n);
   hipLaunchKernelGGL(k_mse, dim3(nblk(n)), dim3(256), 0, s, W.O.p, ranks, n, W.normd.p, W.dO.p, W.se.p);
-  hipLaunchKernelGGL(k_dense_bwd_w, dim3(nblk(NH + 1)), dim3(256), 0, s, W.dO.p, n, 1, W.H3.p, NH, sc, G + OFF_W4,
+  hipLaunchKernelGGL(k_dense_bwd_w, dim3(wblk(NH + 1)), dim3(256), 0, s, W.dO.p, n, 1, W.H3.p, NH, sc, G + OFF_W4,
                      G + OFF_B4);
   hipLaunchKernelGGL(k_dense_bwd_x, dim3(nblk(int64_t(n) * NH)), dim3(256), 0, s, W.dO.p, n, 1, P + OFF_W4, NH, W.H3.p,
                      1, W.dH3.p);
-  hipLaunchKernelGGL(k_dense_bwd_w, dim3(nblk(NH * NH + NH)), dim3(256), 0, s, W.dH3.p, n, NH, W.H2.p, NH, sc,
+  hipLaunchKernelGGL(k_dense_bwd_w, dim3(wblk(NH * NH + NH)), dim3(256), 0, s, W.dH3.p, n, NH, W.H2.p, NH, sc,
                      G + OFF_W3, G + OFF_B3);
   hipLaunchKernelGGL(k_dense_bwd_x, dim3(nblk(int64_t(n) * NH)), dim3(256), 0, s, W.dH3.p, n, NH, P + OFF_W3, NH,
                      W.H2.p, 1, W.dH2.p);
-  hipLaunchKernelGGL(k_dense_bwd_w, dim3(nblk(NH * NH + NH)), dim3(256), 0, s, W.dH2.p, n, NH, W.H1.p, NH, sc,
+  hipLaunchKernelGGL(k_dense_bwd_w, dim3(wblk(NH * NH + NH)), dim3(256), 0, s, W.dH2.p, n, NH, W.H1.p, NH, sc,
                      G + OFF_W2, G + OFF_B2);
   hipLaunchKernelGGL(k_dense_bwd_x, dim3(nblk(int64_t(n) * NH)), dim3(256), 0, s, W.dH2.p, n, NH, P + OFF_W2, NH,
                      W.H1.p, 1, W.dH1.p);
-  hipLaunchKernelGGL(k_dense_bwd_w, dim3(nblk(NH * NF + NH)), dim3(256), 0, s, W.dH1.p, n, NH, W.Z.p, NF, sc,
+  hipLaunchKernelGGL(k_dense_bwd_w, dim3(wblk(NH * NF + NH)), dim3(256), 0, s, W.dH1.p, n, NH, W.Z.p, NF, sc,
                      G + OFF_W1, G + OFF_B1);
   HM_CHECK_HIP(hipGetLastError());
 }

@@ -16,6 +16,7 @@
 #include <cstring>
 #include <future>
 #include <memory>
+#include <mutex>
 #include <numeric>
 
 #include "compress.h"
@@ -109,7 +110,7 @@ void build_kpref(const HMat* M, const DfsInfo& d, DevMat& dm, hipStream_t s) {
 struct Coef {
   double a = 0, b = 0, f = 0;
 };
-enum { K_TERM = 0, K_LEAF = 1, K_EXPAND = 2, K_GATHER = 3, K_COMPRESS = 4, K_FUSED = 5 };
+enum { K_TERM = 0, K_LEAF = 1, K_EXPAND = 2, K_GATHER = 3, K_COMPRESS = 4, K_FUSED = 5, K_FUSED4 = 6 };
 // targets whose clusters both have at most FUSED_MAX (one wave) or FUSED4_MAX (four
 // waves) rows use the fused MFMA kernels
 constexpr int FUSED_MAX = 64;
@@ -125,12 +126,32 @@ struct SubSums {
 struct KernTimer {
   bool on = false;
   hipStream_t s = 0;
+  // events are created once and reused by later products (creation is costly)
+  static std::vector<hipEvent_t>& pool() {
+    static std::vector<hipEvent_t> p;
+    return p;
+  }
+  static std::mutex& pool_mu() {
+    static std::mutex m;
+    return m;
+  }
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
+  hipEvent_t get() {
+    {
+      std::lock_guard<std::mutex> lk(pool_mu());
+      if (!pool().empty()) {
+        hipEvent_t e = pool().back();
+        pool().pop_back();
+        return e;
+      }
+    }
+    hipEvent_t e;
+    HM_CHECK_HIP(hipEventCreate(&e));
+    return e;
+  }
   void begin(int kind) {
     if (!on) return;
-    hipEvent_t a, b;
-    HM_CHECK_HIP(hipEventCreate(&a));
-    HM_CHECK_HIP(hipEventCreate(&b));
+    hipEvent_t a = get(), b = get();
     HM_CHECK_HIP(hipEventRecord(a, s));
     ev.push_back({kind, {a, b}});
   }
@@ -141,13 +162,14 @@ struct KernTimer {
   void resolve(hmat_stats& st) {
     if (!on) return;
     HM_CHECK_HIP(hipStreamSynchronize(s));
+    std::lock_guard<std::mutex> lk(pool_mu());
     for (auto& e : ev) {
       float ms = 0.f;
       HM_CHECK_HIP(hipEventElapsedTime(&ms, e.second.first, e.second.second));
       st.kern_time[e.first] += 1e-3 * ms;
       st.kern_launches[e.first] += 1;
-      (void)hipEventDestroy(e.second.first);
-      (void)hipEventDestroy(e.second.second);
+      pool().push_back(e.second.first);
+      pool().push_back(e.second.second);
     }
     ev.clear();
   }
@@ -631,7 +653,7 @@ void build_chunk(const Ctx& c, Chunk& ch, bool features) {
     const double mt = t.c_size[t.b_tau[b]], nt_ = t.c_size[t.b_sigma[b]];
     const bool small1 = mt <= FUSED_MAX && nt_ <= FUSED_MAX;
     const bool small = mt <= FUSED4_MAX && nt_ <= FUSED4_MAX;
-    ch.is_small[i] = small;
+    ch.is_small[i] = small1 ? 1 : small ? 2 : 0;
     if (small1) ch.small.push_back(i);
     else if (small) ch.small4.push_back(i);
     double skl = 0, skr = 0;
@@ -748,8 +770,9 @@ void run_pass(Ctx& c, Chunk& ch, const std::vector<TDesc>& td, bool trans) {
       account(c.st, K_LEAF, ch.coef[K_LEAF][d][i], td[i].w);
       account(c.st, K_EXPAND, ch.coef[K_EXPAND][d][i], td[i].w);
       if (ch.is_small[i]) {
-        account(c.st, K_FUSED, ch.coef[K_TERM][d][i], td[i].w);
-        account(c.st, K_FUSED, ch.coef[K_GATHER][d][i], td[i].w);
+        const int kf = ch.is_small[i] == 1 ? K_FUSED : K_FUSED4;
+        account(c.st, kf, ch.coef[K_TERM][d][i], td[i].w);
+        account(c.st, kf, ch.coef[K_GATHER][d][i], td[i].w);
       } else {
         account(c.st, K_TERM, ch.coef[K_TERM][d][i], td[i].w);
         account(c.st, K_GATHER, ch.coef[K_GATHER][d][i], td[i].w);
@@ -773,11 +796,14 @@ void run_pass(Ctx& c, Chunk& ch, const std::vector<TDesc>& td, bool trans) {
     launch_gather_mfma(trans ? ch.d_gt.p : ch.d_gf.p, ng, dtd, ch.d_info.p, ch.d_pairs.p, c.tv, ch.vbuf.p, s);
     c.timer.end();
   }
-  if (!ch.small.empty() || !ch.small4.empty()) {
+  if (!ch.small.empty()) {
     c.timer.begin(K_FUSED);
-    if (!ch.small.empty()) launch_fused_terms(ch.d_small.p, ch.small.size(), dtd, ch.d_info.p, ch.d_pairs.p, c.tv, s);
-    if (!ch.small4.empty())
-      launch_fused_terms4(ch.d_small4.p, ch.small4.size(), dtd, ch.d_info.p, ch.d_pairs.p, c.tv, s);
+    launch_fused_terms(ch.d_small.p, ch.small.size(), dtd, ch.d_info.p, ch.d_pairs.p, c.tv, s);
+    c.timer.end();
+  }
+  if (!ch.small4.empty()) {
+    c.timer.begin(K_FUSED4);
+    launch_fused_terms4(ch.d_small4.p, ch.small4.size(), dtd, ch.d_info.p, ch.d_pairs.p, c.tv, s);
     c.timer.end();
   }
 }
@@ -1122,8 +1148,7 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   // first; this is the same order at the granularity of a batch of subtrees).
   int64_t term_budget;
   {
-    size_t fb = 0, tb = 0;
-    HM_CHECK_HIP(hipMemGetInfo(&fb, &tb));
+    const size_t fb = dev_free_bytes();
     term_budget = opts.o.workspace_limit > 0 ? 8 * opts.o.workspace_limit : int64_t(0.45 * double(fb));
   }
   const int depth = t->depth;
@@ -1253,7 +1278,13 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
           for (size_t i = 0; i < w0.size(); ++i) {
             const int mn = std::min(c.m_of(ch.blocks[i]), c.n_of(ch.blocks[i]));
             const double pr = std::isfinite(pred[i]) ? std::ceil(double(pred[i])) : double(opts.o.b0);
-            w0[i] = int32_t(std::clamp(pr + opts.o.p_l, 1.0, double(std::min(mn, 64 - opts.o.probes))));
+            const int g = opts.o.probes;
+            int w = int(std::clamp(pr + opts.o.p_l, 1.0, double(64 - g)));
+            // operator passes run PW columns at a time: widen the sketch as far as it
+            // costs no extra pass of the sketch (w + g columns) or of the projection (w)
+            const int up_s = (w + g + PW - 1) / PW * PW - g, up_p = (w + PW - 1) / PW * PW;
+            w = std::min({up_s, up_p, 64 - g});
+            w0[i] = int32_t(std::max(1, std::min(w, mn)));
           }
           c.st.t_predict += now_seconds() - tq;
         }

@@ -17,10 +17,12 @@ HMAT_OK, HMAT_ERR_ARG, HMAT_ERR_TREE_MISMATCH, HMAT_ERR_NOT_CONVERGED = 0, 1, 2,
 HMAT_ERR_DEVICE, HMAT_ERR_OOM, HMAT_ERR_INTERNAL = 4, 5, 6
 HMAT_FP64, HMAT_FP32_APPLY, HMAT_BF16_SKETCH = 0, 1, 2
 HMAT_RANK_ADAPTIVE, HMAT_RANK_PREDICT = 0, 1
-KERN_NAMES = ["term_reduce", "leaf_reduce", "subtree_expand", "gather", "compress", "fused_terms", "k6", "k7"]
-# device kernels of each family (the fused family is k_fused_terms and k_fused_terms4)
+KERN_NAMES = ["term_reduce", "leaf_reduce", "subtree_expand", "gather", "compress", "fused_terms", "fused_terms4",
+              "k7"]
+# device kernel(s) of each timed family
 KERN_SYMBOLS = ["k_term_reduce", "k_leaf_reduce", "k_subtree_expand", "k_gather_mfma",
-                "k_orth_append+k_probe_residual+k_check+k_core+k_write_factors", "k_fused_terms*", "", ""]
+                "k_orth_append+k_probe_residual+k_check+k_core+k_write_factors", "k_fused_terms",
+                "k_fused_terms4", ""]
 KERNELS = {"laplace_4pi": 0, "inv_dist": 1, "exp": 2}
 
 
