@@ -163,6 +163,14 @@ typedef struct {
    * inside the compression loop, [4] term-pool allocation, [5] creation-list
    * upload, [6] creation kernels incl. synchronisation, [7] term publication. */
   double t_host[8];
+  /* device memory of the product: seconds in hipMalloc/hipFree, hipMalloc calls,
+   * times the block cache was emptied to make room */
+  double t_alloc;
+  int64_t n_malloc;
+  int64_t n_cache_release;
+  /* operator applications: sum over passes of the targets taking part (a pass
+   * applies a target's sum-expression, or its transpose, to up to 16 columns) */
+  int64_t target_passes;
 } hmat_stats;
 
 /* Kernel families of hmat_stats.kern_* */
@@ -183,7 +191,7 @@ typedef struct {
   int32_t growth;      /* columns added per growth round (default 8) */
   int32_t probes;      /* probe columns of the a-posteriori check (default 8) */
   int32_t max_growth;  /* growth rounds before HMAT_ERR_NOT_CONVERGED (default 6) */
-  int32_t p_l;         /* oversampling added to a predicted rank (default 2) */
+  int32_t p_l;         /* oversampling added to a predicted rank (default 3) */
   int32_t time_kernels;/* 1: time every kernel launch with HIP events into stats */
   double delta;        /* residual target: E <= delta * eps * ||S||_F (default 0.2) */
   uint64_t seed;       /* random stream of the sketches (default 0x5eed) */

@@ -31,7 +31,8 @@ static void* g_ctx = nullptr;
 // its (rounded) size class and an event recorded on the library's current
 // stream; it is handed out again only once that event has completed, so work
 // still queued on the old buffer can never see it reused. On allocation
-// failure the cache is released and the allocation retried.
+// failure idle cached blocks are freed, largest first, and the allocation
+// retried.
 static hipStream_t g_stream = 0;
 struct CachedBlock {
   void* p;
@@ -40,7 +41,6 @@ struct CachedBlock {
 static std::map<std::pair<int, size_t>, std::vector<CachedBlock>> g_cache;
 static std::unordered_map<void*, std::pair<int, size_t>> g_live;
 static size_t g_cached_bytes = 0;
-static const size_t kCacheLimit = size_t(64) << 30;
 
 void set_current_stream(hipStream_t s) { g_stream = s; }
 
@@ -61,15 +61,43 @@ static size_t round_size(size_t b) {
   return (b + g - 1) / g * g;
 }
 
-static void release_cache_locked() {
-  for (auto& kv : g_cache)
-    for (auto& cb : kv.second) {
-      (void)hipEventSynchronize(cb.ev);
-      (void)hipEventDestroy(cb.ev);
-      (void)hipFree(cb.p);
+static AllocCounters g_cnt;
+AllocCounters alloc_counters() {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  return g_cnt;
+}
+
+// Frees idle cached blocks, largest first, until at least `need` bytes were
+// returned to the device (everything for SIZE_MAX).
+static void release_some_locked(size_t need) {
+  const double t0 = now_seconds();
+  g_cnt.releases++;
+  size_t freed = 0;
+  while (freed < need && !g_cache.empty()) {
+    auto it = std::prev(g_cache.end());
+    auto& v = it->second;
+    while (!v.empty() && freed < need) {
+      (void)hipEventSynchronize(v.back().ev);
+      (void)hipEventDestroy(v.back().ev);
+      (void)hipFree(v.back().p);
+      v.pop_back();
+      freed += it->first.second;
+      g_cached_bytes -= it->first.second;
     }
-  g_cache.clear();
-  g_cached_bytes = 0;
+    if (v.empty()) g_cache.erase(it);
+  }
+  g_cnt.seconds += now_seconds() - t0;
+}
+
+
+// Upper bound of the cache: 60 % of the device memory (queried once).
+static size_t cache_limit() {
+  static size_t lim = 0;
+  if (!lim) {
+    size_t fb = 0, tb = 0;
+    lim = hipMemGetInfo(&fb, &tb) == hipSuccess ? size_t(0.6 * double(tb)) : (size_t(64) << 30);
+  }
+  return lim;
 }
 
 void* dev_alloc(size_t bytes) {
@@ -99,11 +127,16 @@ void* dev_alloc(size_t bytes) {
         return p;
       }
   }
+  const double t0 = now_seconds();
   hipError_t e = hipMalloc(&p, rs);
-  if (e != hipSuccess) {
+  g_cnt.mallocs++;
+  g_cnt.seconds += now_seconds() - t0;
+  for (int attempt = 0; e != hipSuccess && attempt < 2 && g_cached_bytes > 0; ++attempt) {
     (void)hipGetLastError();
-    release_cache_locked();
+    release_some_locked(attempt == 0 ? rs + (size_t(1) << 30) : SIZE_MAX);
+    const double t1 = now_seconds();
     e = hipMalloc(&p, rs);
+    g_cnt.seconds += now_seconds() - t1;
   }
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -135,7 +168,7 @@ void dev_free(void* p) {
   }
   g_cache[key].push_back({p, ev});
   g_cached_bytes += key.second;
-  if (g_cached_bytes > kCacheLimit) release_cache_locked();
+  if (g_cached_bytes > cache_limit()) release_some_locked(g_cached_bytes - cache_limit() / 2);
 }
 
 static std::mutex g_pin_mu;
@@ -256,7 +289,7 @@ void hmat_opts_default(hmat_opts* o) {
   o->growth = 8;
   o->probes = 8;
   o->max_growth = 6;
-  o->p_l = 2;
+  o->p_l = 3;
   o->delta = 0.2;
   o->seed = 0x5eedull;
 }

@@ -40,6 +40,11 @@ void* dev_alloc(size_t bytes);
 void dev_free(void* p);
 // stream on which freed blocks may still be in use (set by every entry point that launches work)
 void set_current_stream(hipStream_t s);
+struct AllocCounters {
+  double seconds = 0;  // in hipMalloc / hipFree
+  int64_t mallocs = 0, releases = 0;
+};
+AllocCounters alloc_counters();
 // device memory available to the library: free memory plus blocks held by its cache
 size_t dev_free_bytes();
 // Copies host memory to the device and waits; large copies go through a pinned

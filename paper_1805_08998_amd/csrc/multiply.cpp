@@ -767,6 +767,7 @@ void run_pass(Ctx& c, Chunk& ch, const std::vector<TDesc>& td, bool trans) {
   const int d = trans ? 1 : 0;
   for (size_t i = 0; i < td.size(); ++i)
     if (td[i].w) {
+      c.st.target_passes++;
       account(c.st, K_LEAF, ch.coef[K_LEAF][d][i], td[i].w);
       account(c.st, K_EXPAND, ch.coef[K_EXPAND][d][i], td[i].w);
       if (ch.is_small[i]) {
@@ -1090,6 +1091,7 @@ void evaluate_chunk(Ctx& c, Chunk& ch, double* cpool, const std::vector<int64_t>
 
 hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout) {
   const double t_start = now_seconds();
+  const AllocCounters alloc0 = alloc_counters();
   HM_REQUIRE(A->tree == B->tree, HMAT_ERR_TREE_MISMATCH, "A and B must be built on the same tree");
   Tree* t = A->tree;
   HM_REQUIRE(t->leaf_size <= 64, HMAT_ERR_ARG, "the product needs leaf_size <= 64");
@@ -1148,8 +1150,12 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   // first; this is the same order at the granularity of a batch of subtrees).
   int64_t term_budget;
   {
+    // terms of one subtree batch: at most 0.45 of the available memory and at most
+    // 16 GiB (more batches cost little; very large pools are slow to map and make
+    // the budget depend on what earlier products left in the block cache)
     const size_t fb = dev_free_bytes();
-    term_budget = opts.o.workspace_limit > 0 ? 8 * opts.o.workspace_limit : int64_t(0.45 * double(fb));
+    term_budget = opts.o.workspace_limit > 0 ? 8 * opts.o.workspace_limit
+                                             : std::min<int64_t>(int64_t(0.45 * double(fb)), int64_t(16) << 30);
   }
   const int depth = t->depth;
   std::vector<int64_t> cum(depth + 2, 0);
@@ -1379,6 +1385,12 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   c.st.flops_alg = c.alg_flops;
   c.st.bytes_alg = c.alg_bytes;
   c.st.t_total = now_seconds() - t_start;
+  {
+    const AllocCounters a1 = alloc_counters();
+    c.st.t_alloc = a1.seconds - alloc0.seconds;
+    c.st.n_malloc = a1.mallocs - alloc0.mallocs;
+    c.st.n_cache_release = a1.releases - alloc0.releases;
+  }
   if (opts.o.stats) *opts.o.stats = c.st;
   *Cout = C;
   if (c.st.n_not_converged > 0) {

@@ -47,7 +47,8 @@ class hmat_stats(C.Structure):
                 ("n_not_converged", C.c_int64), ("n_fallback", C.c_int64), ("sketch_columns", C.c_int64),
                 ("peak_bytes", C.c_int64), ("n_batches", C.c_int32), ("rank_hist", C.c_int32 * 65),
                 ("kern_launches", C.c_int64 * 8), ("kern_time", C.c_double * 8), ("kern_bytes", C.c_double * 8),
-                ("kern_flops", C.c_double * 8), ("t_host", C.c_double * 8)]
+                ("kern_flops", C.c_double * 8), ("t_host", C.c_double * 8), ("t_alloc", C.c_double),
+                ("n_malloc", C.c_int64), ("n_cache_release", C.c_int64), ("target_passes", C.c_int64)]
 
     def as_dict(self):
         d = {}

@@ -161,11 +161,13 @@ def test_features_and_learned_mode(H, product_case):
         C1, st1 = multiply(H, t, A, B, eps, rank_mode=H.HMAT_RANK_PREDICT, rank_model=m)
         assert count_bad(H, t, C1, P, eps) == 0
         assert st1.n_not_converged == 0
-        print(f"plain: growth rounds {st0.n_growth_rounds}, grown {st0.n_grown_blocks}, columns {st0.sketch_columns};"
-              f" learned: growth rounds {st1.n_growth_rounds}, grown {st1.n_grown_blocks}, columns"
-              f" {st1.sketch_columns}, fallback {st1.n_fallback}", flush=True)
-        # the gain: far fewer targets need the adaptive growth
+        print(f"plain: growth rounds {st0.n_growth_rounds}, grown {st0.n_grown_blocks}, columns {st0.sketch_columns},"
+              f" target passes {st0.target_passes}; learned: growth rounds {st1.n_growth_rounds}, grown"
+              f" {st1.n_grown_blocks}, columns {st1.sketch_columns}, fallback {st1.n_fallback}, target passes"
+              f" {st1.target_passes}", flush=True)
+        # the gain: fewer targets need the adaptive growth, and fewer operator passes are made
         assert st1.n_grown_blocks < 0.5 * max(st0.n_grown_blocks, 1)
+        assert st1.target_passes < st0.target_passes
         assert 0 <= st1.n_fallback <= st1.n_grown_blocks
         H.hmat_destroy(C1)
     finally:
