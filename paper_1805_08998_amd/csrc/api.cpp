@@ -289,7 +289,7 @@ void hmat_opts_default(hmat_opts* o) {
   o->growth = 8;
   o->probes = 8;
   o->max_growth = 6;
-  o->p_l = 3;
+  o->p_l = 2;
   o->delta = 0.2;
   o->seed = 0x5eedull;
 }
