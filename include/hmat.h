@@ -252,8 +252,9 @@ hmat_status hmat_destroy(hmat M);
  *  opts   nullable (defaults).
  *  C      receives a new H-matrix on the same tree.
  * If farfield blocks exhaust max_growth, C is still returned, their best
- * available factors are stored, stats->n_not_converged counts them and the
- * call returns HMAT_ERR_NOT_CONVERGED.
+ * available factors are stored, stats->n_not_converged counts them,
+ * hmat_block_get reports them with converged = 0, and the call returns
+ * HMAT_ERR_NOT_CONVERGED.
  */
 hmat_status hmat_multiply(hmat A, hmat B, double eps, const hmat_opts* opts, hmat* C);
 
@@ -280,6 +281,8 @@ typedef struct {
   int32_t kind;   /* 1 = farfield (low rank), 2 = nearfield (dense) */
   int32_t rank;   /* farfield rank, 0 for nearfield */
   int32_t block;  /* id in hmat_tree_blocks order */
+  int32_t converged;  /* 0 for a farfield block of a product whose growth budget ran out, else 1 */
+  int32_t pad;
 } hmat_block_desc;
 
 /* Number of leaf blocks (farfield + nearfield), breadth-first leaf order. */
@@ -329,6 +332,9 @@ hmat_status hmat_rank_model_train(hmat_rank_model model, const float* feats, con
 /* Inference: pred host float[m]. */
 hmat_status hmat_rank_model_predict(hmat_rank_model model, const float* feats, int64_t m,
                                     float* pred, void* stream);
+/* Model file (parameters and standardisation, little-endian float32 with a header). */
+hmat_status hmat_rank_model_save(hmat_rank_model model, const char* path);
+hmat_status hmat_rank_model_load(const char* path, hmat_rank_model* out);
 /* Parameters as host floats (count via *len when params is NULL). */
 hmat_status hmat_rank_model_get(hmat_rank_model model, float* params, int64_t* len);
 hmat_status hmat_rank_model_set(hmat_rank_model model, const float* params, int64_t len);

@@ -10,7 +10,7 @@ pair. Algorithm 4 recurses from S(I, I) = {(H, K)} and, at a leaf, truncates
 (farfield) or evaluates (nearfield).
 
 Readings:
-  * Def. 3.1 and the proof of Lemma 4.1 print H where K is meant in places; the
+  * Def. 3.1 and the proof of Lemma 5.1 print H where K is meant in places; the
     pair is (H[tau, rho], K[rho, sigma]).
   * When rho is a leaf cluster (tau and sigma are not), Algorithm 3's loop over
     sons(rho) is empty. Then tau x rho and rho x sigma are both nearfield leaves;

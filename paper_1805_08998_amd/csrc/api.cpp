@@ -502,6 +502,8 @@ hmat_status hmat_block_get(hmat mh, int64_t i, hmat_block_desc* d, double* U, do
   d->kind = t->b_kind[b];
   d->rank = t->b_kind[b] == KIND_F ? M->rank[b] : 0;
   d->block = b;
+  d->converged = (!M->notconv.empty() && M->notconv[b]) ? 0 : 1;
+  d->pad = 0;
   if (t->b_kind[b] == KIND_F) {
     int64_t k = M->rank[b];
     if (U && k) HM_CHECK_HIP(hipMemcpy(U, M->pool.p + M->off[b], 8 * k * d->rows, hipMemcpyDeviceToHost));

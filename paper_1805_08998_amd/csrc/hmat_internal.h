@@ -145,6 +145,7 @@ struct HMat {
   // leaf's data in `pool` (-1 for inner blocks)
   std::vector<int32_t> rank;
   std::vector<int64_t> off;
+  std::vector<uint8_t> notconv;  // per block: 1 for a farfield block whose compression did not converge
   int64_t pool_len = 0;
   DevBuf<double> pool;
   DevBuf<int32_t> d_rank;

@@ -408,6 +408,48 @@ hmat_status hmat_rank_model_predict(hmat_rank_model m, const float* feats, int64
   API_END
 }
 
+static const char kModelMagic[8] = {'H', 'M', 'R', 'K', 'M', 'L', 'P', '1'};
+
+hmat_status hmat_rank_model_save(hmat_rank_model m, const char* path) {
+  API_BEGIN
+  HM_REQUIRE(m && path, HMAT_ERR_ARG, "NULL argument");
+  RankModel& M = *reinterpret_cast<RankModel*>(m);
+  std::vector<float> p(NPARAM + NNORM);
+  HM_CHECK_HIP(hipMemcpy(p.data(), M.p.p, 4 * NPARAM, hipMemcpyDeviceToHost));
+  std::memcpy(p.data() + NPARAM, M.norm.data(), 4 * NNORM);
+  FILE* f = std::fopen(path, "wb");
+  HM_REQUIRE(f, HMAT_ERR_ARG, std::string("cannot open ") + path);
+  const int32_t cnt = NPARAM + NNORM;
+  const bool ok = std::fwrite(kModelMagic, 1, 8, f) == 8 && std::fwrite(&cnt, 4, 1, f) == 1 &&
+                  std::fwrite(p.data(), 4, p.size(), f) == p.size();
+  std::fclose(f);
+  HM_REQUIRE(ok, HMAT_ERR_ARG, std::string("write failed: ") + path);
+  API_END
+}
+
+hmat_status hmat_rank_model_load(const char* path, hmat_rank_model* out) {
+  API_BEGIN
+  HM_REQUIRE(path && out, HMAT_ERR_ARG, "NULL argument");
+  FILE* f = std::fopen(path, "rb");
+  HM_REQUIRE(f, HMAT_ERR_ARG, std::string("cannot open ") + path);
+  char magic[8] = {};
+  int32_t cnt = 0;
+  std::vector<float> p(NPARAM + NNORM);
+  const bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kModelMagic, 8) == 0 &&
+                  std::fread(&cnt, 4, 1, f) == 1 && cnt == NPARAM + NNORM &&
+                  std::fread(p.data(), 4, p.size(), f) == p.size();
+  std::fclose(f);
+  HM_REQUIRE(ok, HMAT_ERR_ARG, std::string("not a rank model file: ") + path);
+  hmat_rank_model m = nullptr;
+  const hmat_status st = hmat_rank_model_create(0, &m);
+  if (st != HMAT_OK) return st;
+  RankModel& M = *reinterpret_cast<RankModel*>(m);
+  M.p.upload(p.data(), NPARAM, 0);
+  M.norm.assign(p.begin() + NPARAM, p.end());
+  *out = m;
+  API_END
+}
+
 hmat_status hmat_product_features(hmat C, float* feats, float* ranks, int64_t* count) {
   API_BEGIN
   HM_REQUIRE(C && count, HMAT_ERR_ARG, "NULL argument");

@@ -812,6 +812,7 @@ void run_pass(Ctx& c, Chunk& ch, const std::vector<TDesc>& td, bool trans) {
 struct FarOut {
   DevBuf<double> buf;
   std::vector<int32_t> blocks, ranks;
+  std::vector<uint8_t> done;
   std::vector<int64_t> offs;
   int64_t len = 0;
 };
@@ -1017,6 +1018,7 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
   fetch();
   out.blocks.clear();
   out.ranks.clear();
+  out.done.clear();
   out.offs.clear();
   out.len = 0;
   for (int i = 0; i < nt; ++i) {
@@ -1025,6 +1027,7 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
     if (T.rounds > 0 && c.opts.o.rank_mode == HMAT_RANK_PREDICT) c.st.n_fallback++;
     out.blocks.push_back(T.block);
     out.ranks.push_back(T.k);
+    out.done.push_back(uint8_t(T.done ? 1 : 0));
     out.offs.push_back(out.len);
     T.out_off = out.len;
     out.len += int64_t(T.k) * (T.m + T.n);
@@ -1377,6 +1380,10 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     for (size_t j = 0; j < o.blocks.size(); ++j) {
       C->rank[o.blocks[j]] = o.ranks[j];
       C->off[o.blocks[j]] = base[k] + o.offs[j];
+      if (!o.done[j]) {
+        if (C->notconv.empty()) C->notconv.assign(nb, 0);
+        C->notconv[o.blocks[j]] = 1;
+      }
     }
   }
   C->upload_meta(s);

@@ -72,7 +72,8 @@ class hmat_kernel(C.Structure):
 
 class hmat_block_desc(C.Structure):
     _fields_ = [("row_begin", C.c_int64), ("rows", C.c_int64), ("col_begin", C.c_int64), ("cols", C.c_int64),
-                ("level", C.c_int32), ("kind", C.c_int32), ("rank", C.c_int32), ("block", C.c_int32)]
+                ("level", C.c_int32), ("kind", C.c_int32), ("rank", C.c_int32), ("block", C.c_int32),
+                ("converged", C.c_int32), ("pad", C.c_int32)]
 
 
 class hmat_train_opts(C.Structure):
@@ -113,6 +114,8 @@ _SIGS = {
     "hmat_rank_model_train": (C.c_int32, [_P, _F, _F, C.c_int64, C.POINTER(hmat_train_opts)]),
     "hmat_rank_model_predict": (C.c_int32, [_P, _F, C.c_int64, _F, _P]),
     "hmat_rank_model_get": (C.c_int32, [_P, _F, _I64]),
+    "hmat_rank_model_save": (C.c_int32, [_P, C.c_char_p]),
+    "hmat_rank_model_load": (C.c_int32, [C.c_char_p, _PP]),
     "hmat_rank_model_set": (C.c_int32, [_P, _F, C.c_int64]),
     "hmat_rank_model_grad": (C.c_int32, [_P, _F, _F, C.c_int64, _F, _F]),
     "hmat_product_features": (C.c_int32, [_P, _F, _F, _I64]),
@@ -326,6 +329,16 @@ def hmat_rank_model_predict(model, feats, stream=None):
     f = np.ascontiguousarray(feats, dtype=np.float32)
     out = np.empty(f.shape[0], dtype=np.float32)
     _check(lib().hmat_rank_model_predict(model, _fp(f), f.shape[0], _fp(out), stream))
+    return out
+
+
+def hmat_rank_model_save(model, path):
+    _check(lib().hmat_rank_model_save(model, os.fsencode(path)))
+
+
+def hmat_rank_model_load(path):
+    out = C.c_void_p()
+    _check(lib().hmat_rank_model_load(os.fsencode(path), C.byref(out)))
     return out
 
 

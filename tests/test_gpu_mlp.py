@@ -93,6 +93,26 @@ def test_adam_step_matches_reference(H):
         H.hmat_rank_model_destroy(m)
 
 
+def test_save_load_roundtrip(H, tmp_path):
+    feats, ranks = data(8, 100)
+    m = H.hmat_rank_model_create(2)
+    try:
+        H.hmat_rank_model_set(m, ref_params(H, m, feats, ranks))
+        path = str(tmp_path / "model.bin")
+        H.hmat_rank_model_save(m, path)
+        m2 = H.hmat_rank_model_load(path)
+        try:
+            assert np.array_equal(H.hmat_rank_model_get(m2), H.hmat_rank_model_get(m))
+            assert np.array_equal(H.hmat_rank_model_predict(m2, feats), H.hmat_rank_model_predict(m, feats))
+        finally:
+            H.hmat_rank_model_destroy(m2)
+        (tmp_path / "bad.bin").write_bytes(b"not a model")
+        with pytest.raises(H.HmatError):
+            H.hmat_rank_model_load(str(tmp_path / "bad.bin"))
+    finally:
+        H.hmat_rank_model_destroy(m)
+
+
 def test_training_lowers_loss(H):
     feats, ranks = data(6, 2000)
     m = H.hmat_rank_model_create(9)
@@ -213,6 +233,11 @@ def test_growth_budget_exhausted_is_reported(H, product_case):
     C, code = H.hmat_multiply(A, B, 1e-6, o, allow_not_converged=True)
     assert code == H.HMAT_ERR_NOT_CONVERGED
     assert st.n_not_converged > 0
+    # the blocks are listed: converged = 0 exactly on the farfield blocks that ran out
+    n = H.hmat_block_count(C)
+    flags = [H.hmat_block_get(C, i, with_data=False)[0] for i in range(n)]
+    assert sum(1 for d in flags if d["converged"] == 0) == st.n_not_converged
+    assert all(d["kind"] == 1 for d in flags if d["converged"] == 0)
     H.hmat_destroy(C)
     with pytest.raises(H.HmatError):
         H.hmat_multiply(A, B, 1e-6, o)

@@ -63,7 +63,7 @@ CONFIGS = {
                           jitter=1e-3),
     # n = 262144 ellipsoid (1, 0.7, 0.5), kernels as sphere64k.
     "ellipsoid256k": Workload("ellipsoid256k", 262144, "ellipsoid", 64, 0.8, LAPLACE, EXP_PLUS_I,
-                              1e-8, 1e-6),
+                              1e-8, 1e-6, jitter=1e-3),
     # n = 262144 jittered sphere, kernels as sphere64k (the headline workload).
     "sphere256k": Workload("sphere256k", 262144, "sphere", 64, 0.8, LAPLACE, EXP_PLUS_I, 1e-8, 1e-6,
                            jitter=1e-3),
