@@ -171,6 +171,9 @@ typedef struct {
   /* operator applications: sum over passes of the targets taking part (a pass
    * applies a target's sum-expression, or its transpose, to up to 16 columns) */
   int64_t target_passes;
+  /* hmat_multiply_batched: products in flight at once (chosen or autotuned) */
+  int32_t streams_used;
+  int32_t pad_s;
 } hmat_stats;
 
 /* Kernel families of hmat_stats.kern_* */
@@ -199,6 +202,9 @@ typedef struct {
   hmat_rank_model rank_model;  /* required for HMAT_RANK_PREDICT */
   hmat_stats* stats;   /* optional output */
   int64_t workspace_limit;     /* bytes of device workspace per subtree batch (0 = auto) */
+  int32_t streams;     /* hmat_multiply_batched: products in flight at once, each on its own
+                          stream and host thread (0 = autotuned, default) */
+  int32_t pad;
 } hmat_opts;
 
 /* Fills *o with the defaults listed above. */
@@ -260,7 +266,18 @@ hmat_status hmat_multiply(hmat A, hmat B, double eps, const hmat_opts* opts, hma
 
 /*
  * count independent products C[i] = A[i] B[i] (each pair on its own tree).
- * status (host int32[count], nullable) receives the per-product status.
+ * status (host int32[count], nullable) receives the per-product status; the
+ * return value is the first non-OK status (HMAT_OK if all succeeded) and
+ * hmat_last_error names the first failing product.
+ * Products run concurrently: opts->streams host threads, each with its own
+ * HIP stream (created and destroyed inside the call; opts->stream is not
+ * used), take products in index order. With streams = 0 the count is
+ * autotuned: the first products are run with 1, 2, 4 and 8 streams (2 x
+ * streams products each), the rate (algorithmic flops / wall time) of each
+ * trial is compared, the best count runs the rest and is remembered for
+ * later batches of the same size class (rounded mean log2 n). If
+ * opts->stats is set it receives the sums over all products, with t_total
+ * the wall time of the call and streams_used the count that ran the rest.
  */
 hmat_status hmat_multiply_batched(const hmat* A, const hmat* B, int32_t count, double eps,
                                   const hmat_opts* opts, hmat* C, int32_t* status);

@@ -33,7 +33,7 @@ static void* g_ctx = nullptr;
 // still queued on the old buffer can never see it reused. On allocation
 // failure idle cached blocks are freed, largest first, and the allocation
 // retried.
-static hipStream_t g_stream = 0;
+static thread_local hipStream_t g_stream = 0;  // per host thread (concurrent products)
 struct CachedBlock {
   void* p;
   hipEvent_t ev;
@@ -226,6 +226,7 @@ Opts resolve_opts(const hmat_opts* o) {
              "unknown rank mode");
   HM_REQUIRE(r.o.rank_mode != HMAT_RANK_PREDICT || r.o.rank_model != nullptr, HMAT_ERR_ARG,
              "HMAT_RANK_PREDICT needs opts.rank_model");
+  HM_REQUIRE(r.o.streams >= 0 && r.o.streams <= 16, HMAT_ERR_ARG, "streams must be in [0, 16]");
   return r;
 }
 

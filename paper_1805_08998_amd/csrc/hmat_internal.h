@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <mutex>
 #include <cstdint>
 #include <cstdio>
 #include <stdexcept>
@@ -119,6 +120,7 @@ struct Tree {
 
   DeviceTree* dev = nullptr;
   int dev_id = -1;
+  std::mutex dev_mu;  // guards the lazy device copy
 
   int32_t find_block(int32_t tau, int32_t sigma) const;  // -1 if absent
   bool is_leaf_cluster(int32_t c) const { return c_nchild[c] == 0; }

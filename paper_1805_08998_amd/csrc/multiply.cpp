@@ -15,9 +15,11 @@
 #include <cmath>
 #include <cstring>
 #include <future>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <numeric>
+#include <thread>
 
 #include "compress.h"
 #include "product_kernels.h"
@@ -1407,21 +1409,155 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   return HMAT_OK;
 }
 
+// ------------------------------------------------------------------ batched products
+// Independent products run concurrently, one host thread and one HIP stream per
+// product in flight, so that small products (whose levels are too narrow to fill
+// 256 CUs) overlap. The number in flight is autotuned per size class.
+namespace {
+std::mutex g_tune_mu;
+std::map<int, int> g_tuned_streams;  // size class (rounded mean log2 n) -> streams
+
+void add_stats(hmat_stats& a, const hmat_stats& b) {
+  a.t_plan += b.t_plan;
+  a.t_restrict += b.t_restrict;
+  a.t_sketch += b.t_sketch;
+  a.t_project += b.t_project;
+  a.t_core += b.t_core;
+  a.t_near += b.t_near;
+  a.t_predict += b.t_predict;
+  a.flops_alg += b.flops_alg;
+  a.bytes_alg += b.bytes_alg;
+  a.n_far += b.n_far;
+  a.n_near += b.n_near;
+  a.n_growth_rounds += b.n_growth_rounds;
+  a.n_grown_blocks += b.n_grown_blocks;
+  a.n_not_converged += b.n_not_converged;
+  a.n_fallback += b.n_fallback;
+  a.sketch_columns += b.sketch_columns;
+  a.peak_bytes = std::max(a.peak_bytes, b.peak_bytes);
+  a.n_batches += b.n_batches;
+  for (int k = 0; k < 65; ++k) a.rank_hist[k] += b.rank_hist[k];
+  for (int k = 0; k < 8; ++k) {
+    a.kern_launches[k] += b.kern_launches[k];
+    a.kern_time[k] += b.kern_time[k];
+    a.kern_bytes[k] += b.kern_bytes[k];
+    a.kern_flops[k] += b.kern_flops[k];
+    a.t_host[k] += b.t_host[k];
+  }
+  a.t_alloc += b.t_alloc;
+  a.n_malloc += b.n_malloc;
+  a.n_cache_release += b.n_cache_release;
+  a.target_passes += b.target_passes;
+}
+}  // namespace
+
 hmat_status multiply_batched(HMat* const* A, HMat* const* B, int32_t count, double eps, const Opts& opts,
                              HMat** C, int32_t* status) {
-  hmat_status worst = HMAT_OK;
+  const double t0 = now_seconds();
+  int dev = 0;
+  HM_CHECK_HIP(hipGetDevice(&dev));
   for (int32_t i = 0; i < count; ++i) {
+    HM_REQUIRE(A[i] && B[i], HMAT_ERR_ARG, "NULL H-matrix in batch");
     C[i] = nullptr;
-    hmat_status st;
-    try {
-      st = multiply(A[i], B[i], eps, opts, &C[i]);
-    } catch (const Error& e) {
-      set_last_error(e.what());
-      st = e.code;
-    }
-    if (status) status[i] = st;
-    if (st != HMAT_OK && worst == HMAT_OK) worst = st;
   }
+  std::vector<hmat_stats> pst(size_t(std::max(count, 1)));
+  std::vector<hmat_status> pstat(size_t(std::max(count, 1)), HMAT_OK);
+  std::vector<std::string> perr(size_t(std::max(count, 1)));
+  // products [lo, hi) on S streams; returns the wall time
+  auto run_range = [&](int32_t lo, int32_t hi, int S) {
+    std::atomic<int32_t> next{lo};
+    std::vector<std::thread> th;
+    const double ts = now_seconds();
+    for (int w = 0; w < S; ++w)
+      th.emplace_back([&]() {
+        hipStream_t s = nullptr;
+        if (hipSetDevice(dev) != hipSuccess || hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+          (void)hipGetLastError();
+          s = nullptr;
+        }
+        for (;;) {
+          const int32_t i = next.fetch_add(1);
+          if (i >= hi) break;
+          if (!s) {
+            pstat[i] = HMAT_ERR_DEVICE;
+            perr[i] = "stream creation failed";
+            continue;
+          }
+          Opts o = opts;
+          o.o.stream = s;
+          o.o.stats = &pst[i];
+          try {
+            pstat[i] = multiply(A[i], B[i], eps, o, &C[i]);
+            if (pstat[i] != HMAT_OK) perr[i] = "product " + std::to_string(i) + ": " + hmat_last_error();
+          } catch (const Error& e) {
+            pstat[i] = e.code;
+            perr[i] = "product " + std::to_string(i) + ": " + e.what();
+          } catch (const std::exception& e) {
+            pstat[i] = HMAT_ERR_INTERNAL;
+            perr[i] = "product " + std::to_string(i) + ": " + e.what();
+          }
+        }
+        if (s) {
+          (void)hipStreamSynchronize(s);
+          (void)hipStreamDestroy(s);
+        }
+      });
+    for (auto& x : th) x.join();
+    return now_seconds() - ts;
+  };
+  int S = opts.o.streams;
+  int32_t done = 0;
+  if (count > 0 && S <= 0) {
+    double lg = 0;
+    for (int32_t i = 0; i < count; ++i) lg += std::log2(double(std::max<int64_t>(A[i]->tree->n, 2)));
+    const int cls = int(std::lround(lg / count));
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tuned_streams.find(cls);
+      if (it != g_tuned_streams.end()) S = it->second;
+    }
+    if (S <= 0) {
+      // trials: 2 x S products each with S = 1, 2, 4, 8; the best rate runs the rest
+      double best = -1.0;
+      int best_s = 1;
+      bool complete = true;
+      for (int cand : {1, 2, 4, 8}) {
+        const int32_t take = std::min<int32_t>(2 * cand, count - done);
+        if (take < cand) {
+          complete = false;
+          break;
+        }
+        const double sec = run_range(done, done + take, cand);
+        double fl = 0;
+        for (int32_t i = done; i < done + take; ++i) fl += pst[i].flops_alg;
+        const double rate = fl / std::max(sec, 1e-9);
+        if (rate > best) best = rate, best_s = cand;
+        done += take;
+      }
+      S = best_s;
+      if (complete) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned_streams[cls] = S;
+      }
+    }
+  }
+  if (S <= 0) S = 1;
+  if (done < count) run_range(done, count, std::min<int>(S, count - done));
+  hmat_status worst = HMAT_OK;
+  std::string first_err;
+  hmat_stats tot{};
+  for (int32_t i = 0; i < count; ++i) {
+    if (status) status[i] = pstat[i];
+    if (pstat[i] != HMAT_OK && worst == HMAT_OK) {
+      worst = pstat[i];
+      first_err = perr[i];
+    }
+    add_stats(tot, pst[i]);
+  }
+  tot.t_total = now_seconds() - t0;
+  tot.streams_used = S;
+  if (opts.o.stats) *opts.o.stats = tot;
+  set_last_error(first_err);
   return worst;
 }
 

@@ -226,6 +226,7 @@ Tree* build_tree(const double* xyz, int64_t n, int32_t leaf, double eta, int32_t
 }
 
 void Tree::ensure_device(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(dev_mu);
   int d = 0;
   HM_CHECK_HIP(hipGetDevice(&d));
   if (dev && dev_id == d) return;
