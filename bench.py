@@ -48,13 +48,16 @@ def leaf_arrays(H, tree):
                 level=bl["level"][ids])
 
 
-def cpu_baseline(H, tree, A, B, eps, flops_alg, seconds=20.0, max_rows=256, seed=0):
+def cpu_baseline(H, tree, A, B, eps, flops_alg, seconds=20.0, max_rows=256, seed=0, C=None):
     """The CPU oracle (exact block from densified strips of the library's A_H and
     B_H, singular values for farfield blocks) timed on a stratified sample: per
     (level, kind) a few leaves of at most max_rows rows. The oracle's time for
     the whole product is estimated level by level from its measured rate in
     exact-block entries per second (levels without sample use the nearest
-    sampled level), and reported as effective GFLOP/s on the same flop count."""
+    sampled level), and reported as effective GFLOP/s on the same flop count.
+    With C (the library's product), each sampled exact block is also compared
+    with C's block after the timing: relative error / eps and rank - eps-rank
+    for farfield blocks, relative error for nearfield blocks."""
     from oracle.product import LeafStrips, oracle_block
     try:
         from threadpoolctl import threadpool_info
@@ -71,6 +74,7 @@ def cpu_baseline(H, tree, A, B, eps, flops_alg, seconds=20.0, max_rows=256, seed
         return LeafStrips(n, la["r0"], la["r1"], la["c0"], la["c1"], get)
 
     sa, sb = src(A), src(B)
+    parity = {"far_err": [], "slack": [], "near_err": []}
     rng = np.random.default_rng(seed)
     levels = np.unique(la["level"])
     rates = {}
@@ -91,8 +95,17 @@ def cpu_baseline(H, tree, A, B, eps, flops_alg, seconds=20.0, max_rows=256, seed
                 for j in sb.cols_needed(c0, c1):
                     sb.leaf(j)
                 ts = time.perf_counter()
-                oracle_block(sa, sb, r0, r1, c0, c1, kind, eps)
+                D, sv, kstar = oracle_block(sa, sb, r0, r1, c0, c1, kind, eps)
                 dt = time.perf_counter() - ts
+                if C is not None:
+                    d, U, V = H.hmat_block_get(C, int(i))
+                    nd = float(np.linalg.norm(D))
+                    if kind == 1:
+                        e = float(np.linalg.norm(D - U @ V.T)) / max(nd, 1e-300)
+                        parity["far_err"].append(e / eps)
+                        parity["slack"].append(int(d["rank"]) - int(kstar))
+                    else:
+                        parity["near_err"].append(float(np.linalg.norm(D - V)) / max(nd, 1e-300))
                 ent += float((r1 - r0) * (c1 - c0))
                 tt += dt
                 sampled += 1
@@ -116,7 +129,7 @@ def cpu_baseline(H, tree, A, B, eps, flops_alg, seconds=20.0, max_rows=256, seed
                 same = [k for k in keys if k[1] == kind] or keys
                 key = min(same, key=lambda k: abs(k[0] - L))
             t_est += ents / rates[key]
-    return {
+    out = {
         "value": flops_alg / t_est / 1e9,
         "unit": "GFLOP/s (effective, same flop count as value)",
         "cores": int(cores),
@@ -127,6 +140,18 @@ def cpu_baseline(H, tree, A, B, eps, flops_alg, seconds=20.0, max_rows=256, seed
                   f"from per-level entry rates",
         "oracle_seconds_estimated": t_est,
     }
+    if C is not None and parity["far_err"]:
+        fe = np.array(parity["far_err"])
+        sl = np.array(parity["slack"])
+        ne = np.array(parity["near_err"]) if parity["near_err"] else np.zeros(1)
+        out["sampled_parity"] = {
+            "blocks_far": int(fe.size), "blocks_near": len(parity["near_err"]),
+            "far_err_over_eps_max": float(fe.max()), "far_err_over_eps_p99": float(np.percentile(fe, 99)),
+            "far_err_over_eps_median": float(np.median(fe)), "rank_minus_kstar_max": int(sl.max()),
+            "near_rel_err_max": float(ne.max()),
+            "far_outside_bound": int(np.sum((fe > 1.01) | (sl > 2))),
+        }
+    return out
 
 
 def train_predictor(H, configs, names, epochs, cache=None):
@@ -204,6 +229,9 @@ def run_batched(H, args):
             if c.value:
                 H.hmat_destroy(c)
         bad = int(np.sum(status != 0))
+        if bad:
+            codes = {int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))}
+            log(f"[bench] batched: statuses {codes}: {H.lib().hmat_last_error().decode()}")
         return dt, st.as_dict(), bad
 
     for i in range(max(1, args.warmup)):
@@ -329,13 +357,10 @@ def main():
     log(f"[bench] instrumented step: {kdt:.3f}s")
     plain = None
     if args.mode == "learned" and args.compare_steps > 0:
-        H.hmat_destroy(C)
-        C = None
         pt = []
         for i in range(args.compare_steps):
-            if C is not None:
-                H.hmat_destroy(C)
-            C, pst, dt = run(False, "plain")
+            Cp, pst, dt = run(False, "plain")
+            H.hmat_destroy(Cp)
             pt.append(dt)
             log(f"[bench] plain step {i}: {dt:.3f}s batches {pst['n_batches']} grown {pst['n_grown_blocks']} "
                 f"columns {pst['sketch_columns']} sketch {pst['t_sketch']:.3f} project {pst['t_project']:.3f}")
@@ -378,7 +403,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         try:
-            cpu = cpu_baseline(H, tree, A, B, w.eps, flops, seconds=args.cpu_seconds)
+            cpu = cpu_baseline(H, tree, A, B, w.eps, flops, seconds=args.cpu_seconds, C=C)
         except Exception as e:  # the baseline is reported, never the target
             log(f"[bench] cpu baseline failed: {e!r}")
     out = {

@@ -128,6 +128,17 @@ hmat_status hmat_tree_blocks(hmat_tree t, int32_t* tau, int32_t* sigma, int32_t*
 /* Options and statistics                                                   */
 /* ------------------------------------------------------------------------ */
 
+/*
+ * Precision of the sum-expression applies:
+ *  HMAT_FP64        everything in float64;
+ *  HMAT_FP32_APPLY  the forward sketch and probe passes read float32 copies of
+ *                   every panel (inputs and created terms; arithmetic stays
+ *                   float64 on MFMA), while projection, orthogonalisation,
+ *                   core SVD, truncation and the nearfield stay float64; the
+ *                   float copies of A and B are kept with the matrices;
+ *  HMAT_BF16_SKETCH rejected with HMAT_ERR_ARG (bf16 panels perturb S by about
+ *                   4e-3 relative, above every supported tolerance).
+ */
 enum { HMAT_FP64 = 0, HMAT_FP32_APPLY = 1, HMAT_BF16_SKETCH = 2 };
 enum { HMAT_RANK_ADAPTIVE = 0, HMAT_RANK_PREDICT = 1 };
 
@@ -188,7 +199,7 @@ enum {
 };
 
 typedef struct {
-  int32_t precision;   /* HMAT_FP64 (default), HMAT_FP32_APPLY, HMAT_BF16_SKETCH */
+  int32_t precision;   /* HMAT_FP64 (default) or HMAT_FP32_APPLY */
   int32_t rank_mode;   /* HMAT_RANK_ADAPTIVE (default) or HMAT_RANK_PREDICT */
   int32_t b0;          /* initial sketch width (default 8) */
   int32_t growth;      /* columns added per growth round (default 8) */

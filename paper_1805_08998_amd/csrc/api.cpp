@@ -67,35 +67,47 @@ AllocCounters alloc_counters() {
   return g_cnt;
 }
 
-// Frees idle cached blocks, largest first, until at least `need` bytes were
-// returned to the device (everything for SIZE_MAX).
-static void release_some_locked(size_t need) {
-  const double t0 = now_seconds();
+// Takes cached blocks out of the cache, largest first, until at least `need`
+// bytes are collected (everything for SIZE_MAX). The caller frees them with
+// free_blocks() after dropping the lock, so that waiting for their last use
+// does not stall other threads' allocations.
+static std::vector<CachedBlock> take_blocks_locked(size_t need) {
+  std::vector<CachedBlock> out;
   g_cnt.releases++;
-  size_t freed = 0;
-  while (freed < need && !g_cache.empty()) {
+  size_t got = 0;
+  while (got < need && !g_cache.empty()) {
     auto it = std::prev(g_cache.end());
     auto& v = it->second;
-    while (!v.empty() && freed < need) {
-      (void)hipEventSynchronize(v.back().ev);
-      (void)hipEventDestroy(v.back().ev);
-      (void)hipFree(v.back().p);
+    while (!v.empty() && got < need) {
+      out.push_back(v.back());
       v.pop_back();
-      freed += it->first.second;
+      got += it->first.second;
       g_cached_bytes -= it->first.second;
     }
     if (v.empty()) g_cache.erase(it);
   }
-  g_cnt.seconds += now_seconds() - t0;
+  return out;
 }
 
+static void free_blocks(std::vector<CachedBlock>& v) {
+  const double t0 = now_seconds();
+  for (auto& cb : v) {
+    (void)hipEventSynchronize(cb.ev);
+    (void)hipEventDestroy(cb.ev);
+    (void)hipFree(cb.p);
+  }
+  v.clear();
+  const double dt = now_seconds() - t0;
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_cnt.seconds += dt;
+}
 
-// Upper bound of the cache: 60 % of the device memory (queried once).
+// Upper bound of the cache: a quarter of the device memory (queried once).
 static size_t cache_limit() {
   static size_t lim = 0;
   if (!lim) {
     size_t fb = 0, tb = 0;
-    lim = hipMemGetInfo(&fb, &tb) == hipSuccess ? size_t(0.6 * double(tb)) : (size_t(64) << 30);
+    lim = hipMemGetInfo(&fb, &tb) == hipSuccess ? size_t(0.25 * double(tb)) : (size_t(32) << 30);
   }
   return lim;
 }
@@ -103,41 +115,50 @@ static size_t cache_limit() {
 void* dev_alloc(size_t bytes) {
   void* p = nullptr;
   if (bytes == 0) bytes = 8;
-  std::lock_guard<std::mutex> lk(g_alloc_mu);
-  if (g_alloc) {
-    p = g_alloc(bytes, g_ctx);
-    if (!p) throw Error(HMAT_ERR_OOM, "allocator hook failed for " + std::to_string(bytes) + " bytes");
-    return p;
-  }
   int dev = 0;
   (void)hipGetDevice(&dev);
   const size_t rs = round_size(bytes);
-  // best fit: the smallest cached size class of at least rs and at most 1.5 rs
-  for (auto it = g_cache.lower_bound({dev, rs});
-       it != g_cache.end() && it->first.first == dev && it->first.second <= rs + rs / 2; ++it) {
-    auto& v = it->second;
-    for (size_t i = 0; i < v.size(); ++i)
-      if (hipEventQuery(v[i].ev) == hipSuccess) {
-        p = v[i].p;
-        const size_t got = it->first.second;
-        (void)hipEventDestroy(v[i].ev);
-        v.erase(v.begin() + i);
-        g_cached_bytes -= got;
-        g_live[p] = {dev, got};
-        return p;
-      }
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    if (g_alloc) {
+      p = g_alloc(bytes, g_ctx);
+      if (!p) throw Error(HMAT_ERR_OOM, "allocator hook failed for " + std::to_string(bytes) + " bytes");
+      return p;
+    }
+    // best fit: the smallest cached size class of at least rs and at most 1.5 rs whose
+    // last use has completed
+    for (auto it = g_cache.lower_bound({dev, rs});
+         it != g_cache.end() && it->first.first == dev && it->first.second <= rs + rs / 2; ++it) {
+      auto& v = it->second;
+      for (size_t i = 0; i < v.size(); ++i)
+        if (hipEventQuery(v[i].ev) == hipSuccess) {
+          p = v[i].p;
+          const size_t got = it->first.second;
+          (void)hipEventDestroy(v[i].ev);
+          v.erase(v.begin() + i);
+          g_cached_bytes -= got;
+          g_live[p] = {dev, got};
+          return p;
+        }
+    }
   }
   const double t0 = now_seconds();
   hipError_t e = hipMalloc(&p, rs);
-  g_cnt.mallocs++;
-  g_cnt.seconds += now_seconds() - t0;
-  for (int attempt = 0; e != hipSuccess && attempt < 2 && g_cached_bytes > 0; ++attempt) {
+  const double t1 = now_seconds();
+  for (int attempt = 0; e != hipSuccess && attempt < 2; ++attempt) {
     (void)hipGetLastError();
-    release_some_locked(attempt == 0 ? rs + (size_t(1) << 30) : SIZE_MAX);
-    const double t1 = now_seconds();
+    std::vector<CachedBlock> victims;
+    {
+      std::lock_guard<std::mutex> lk(g_alloc_mu);
+      if (g_cached_bytes == 0) break;
+      victims = take_blocks_locked(attempt == 0 ? rs + (size_t(1) << 30) : SIZE_MAX);
+    }
+    free_blocks(victims);
     e = hipMalloc(&p, rs);
-    g_cnt.seconds += now_seconds() - t1;
   }
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_cnt.mallocs++;
+  g_cnt.seconds += t1 - t0;
   if (e != hipSuccess) {
     (void)hipGetLastError();
     throw Error(HMAT_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
@@ -148,27 +169,32 @@ void* dev_alloc(size_t bytes) {
 
 void dev_free(void* p) {
   if (!p) return;
-  std::lock_guard<std::mutex> lk(g_alloc_mu);
-  if (g_free) {
-    g_free(p, g_ctx);
-    return;
+  std::vector<CachedBlock> victims;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    if (g_free) {
+      g_free(p, g_ctx);
+      return;
+    }
+    auto it = g_live.find(p);
+    if (it == g_live.end()) {
+      (void)hipFree(p);
+      return;
+    }
+    const auto key = it->second;
+    g_live.erase(it);
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(ev, g_stream) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipFree(p);
+      return;
+    }
+    g_cache[key].push_back({p, ev});
+    g_cached_bytes += key.second;
+    if (g_cached_bytes > cache_limit()) victims = take_blocks_locked(g_cached_bytes - cache_limit() / 2);
   }
-  auto it = g_live.find(p);
-  if (it == g_live.end()) {
-    (void)hipFree(p);
-    return;
-  }
-  const auto key = it->second;
-  g_live.erase(it);
-  hipEvent_t ev;
-  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev, g_stream) != hipSuccess) {
-    (void)hipGetLastError();
-    (void)hipFree(p);
-    return;
-  }
-  g_cache[key].push_back({p, ev});
-  g_cached_bytes += key.second;
-  if (g_cached_bytes > cache_limit()) release_some_locked(g_cached_bytes - cache_limit() / 2);
+  free_blocks(victims);
 }
 
 static std::mutex g_pin_mu;
@@ -222,6 +248,9 @@ Opts resolve_opts(const hmat_opts* o) {
   HM_REQUIRE(r.o.p_l >= 0 && r.o.p_l <= 16, HMAT_ERR_ARG, "p_l must be in [0, 16]");
   HM_REQUIRE(r.o.delta > 0.0 && r.o.delta <= 1.0, HMAT_ERR_ARG, "delta must be in (0, 1]");
   HM_REQUIRE(r.o.precision >= 0 && r.o.precision <= 2, HMAT_ERR_ARG, "unknown precision");
+  HM_REQUIRE(r.o.precision != HMAT_BF16_SKETCH, HMAT_ERR_ARG,
+             "HMAT_BF16_SKETCH is not supported: bf16 panels perturb S by ~4e-3 relative, far above any "
+             "tolerance the product targets, so the sketch would need as many fp64 growth rounds as it saves");
   HM_REQUIRE(r.o.rank_mode == HMAT_RANK_ADAPTIVE || r.o.rank_mode == HMAT_RANK_PREDICT, HMAT_ERR_ARG,
              "unknown rank mode");
   HM_REQUIRE(r.o.rank_mode != HMAT_RANK_PREDICT || r.o.rank_model != nullptr, HMAT_ERR_ARG,

@@ -153,6 +153,7 @@ struct HMat {
   DevBuf<int32_t> d_rank;
   DevBuf<int64_t> d_off;
   DevBuf<float> pool32;  // float copy of `pool`, built on demand for mixed precision
+  std::mutex mu32;       // guards building pool32
   ProductFeatures features;
   ~HMat();
   void upload_meta(hipStream_t s);

@@ -28,19 +28,20 @@ namespace hm {
 
 void launch_leaf_reduce(const int64_t* pre, int ntask, int64_t nitems, const Task* tasks, const TDesc* td,
                         const int32_t* dfs_block, const TreeView& tv, const MatView& ma, const MatView& mb,
-                        double* ws, hipStream_t s);
+                        double* ws, hipStream_t s, bool lowp);
 void launch_subtree_expand(const int64_t* pre, int ntask, int64_t nitems, const Task* tasks, const TDesc* td,
                            const TreeView& tv, const MatView& ma, const MatView& mb, const double* ws,
-                           hipStream_t s);
+                           hipStream_t s, bool lowp);
 void launch_term_reduce(const TermItem* items, size_t n, const TDesc* td, const TInfo* ti, const TreeView& tv,
-                        double* vbuf, hipStream_t s);
+                        double* vbuf, hipStream_t s, bool lowp);
 void launch_gather_mfma(const RowItem* items, size_t n, const TDesc* td, const TInfo* ti, const HPair* hp,
-                        const TreeView& tv, const double* vbuf, hipStream_t s);
+                        const TreeView& tv, const double* vbuf, hipStream_t s, bool lowp);
 void launch_fused_terms(const int32_t* tlist, size_t n, const TDesc* td, const TInfo* ti, const HPair* hp,
-                        const TreeView& tv, hipStream_t s);
+                        const TreeView& tv, hipStream_t s, bool lowp);
 void launch_scatter_terms(const int32_t* ids, const Term* src, Term* dst, int64_t n, hipStream_t s);
 void launch_fused_terms4(const int32_t* tlist, size_t n, const TDesc* td, const TInfo* ti, const HPair* hp,
-                         const TreeView& tv, hipStream_t s);
+                         const TreeView& tv, hipStream_t s, bool lowp);
+void launch_to_float(const double* src, float* dst, int64_t n, hipStream_t s);
 
 namespace {
 
@@ -94,7 +95,7 @@ DfsInfo dfs_order(const Tree& t) {
 struct DevMat {
   DevBuf<int64_t> kpref;
   std::vector<int64_t> hkpref;
-  MatView view(const HMat* M) const { return MatView{M->pool.p, M->d_rank.p, M->d_off.p, kpref.p}; }
+  MatView view(const HMat* M) const { return MatView{M->pool.p, M->d_rank.p, M->d_off.p, kpref.p, M->pool32.p}; }
 };
 
 void build_kpref(const HMat* M, const DfsInfo& d, DevMat& dm, hipStream_t s) {
@@ -200,6 +201,32 @@ struct Ctx {
   KernTimer timer;
   SubSums sa, sb;
   double alg_flops = 0, alg_bytes = 0;  // minimum algorithmic work (final ranks as widths)
+  // mixed precision: the forward sketch passes read float copies of every panel pool
+  bool lowp = false;
+  struct PoolPair {
+    const double* b64;
+    int64_t len;
+    const float* b32;
+  };
+  std::vector<PoolPair> pools;  // double pool -> its float copy
+  std::vector<Term32> hterms32;
+  DevBuf<Term32> terms32;
+  DevBuf<float> gpool32, bpool32;  // float copies of the created-term pools
+  void register_pool(const double* b64, int64_t len, const float* b32) {
+    for (auto& q : pools)
+      if (q.b64 == b64) {
+        q.len = len;
+        q.b32 = b32;
+        return;
+      }
+    pools.push_back(PoolPair{b64, len, b32});
+  }
+  const float* to32(const double* p) const {
+    if (!p) return nullptr;
+    for (const auto& q : pools)
+      if (p >= q.b64 && p <= q.b64 + q.len) return q.b32 + (p - q.b64);
+    throw Error(HMAT_ERR_INTERNAL, "term panel outside the registered pools");
+  }
 
   int32_t m_of(int32_t b) const { return t->c_size[t->b_tau[b]]; }
   int32_t n_of(int32_t b) const { return t->c_size[t->b_sigma[b]]; }
@@ -382,22 +409,22 @@ int64_t subtree_ws(const Ctx& c, int mat, int32_t q) {
 }
 
 // Leaf reductions (and expansions) of a task list; X and widths of target tasks come from td.
-void run_tasks(Ctx& c, TaskList& L, const TDesc* td, double* ws, bool expand) {
+void run_tasks(Ctx& c, TaskList& L, const TDesc* td, double* ws, bool expand, bool lowp = false) {
   if (L.tasks.empty()) return;
   if (L.lpre.back() > 0) {
     c.timer.begin(K_LEAF);
     launch_leaf_reduce(L.d_lpre.p, L.ntask(), L.lpre.back(), L.d_tasks.p, td, c.d_dfs_block.p, c.tv, c.ma, c.mb, ws,
-                       c.s);
+                       c.s, lowp);
     c.timer.end();
   }
   if (expand && L.rpre.back() > 0) {
     c.timer.begin(K_EXPAND);
-    launch_subtree_expand(L.d_rpre.p, L.ntask(), L.rpre.back(), L.d_tasks.p, td, c.tv, c.ma, c.mb, ws, c.s);
+    launch_subtree_expand(L.d_rpre.p, L.ntask(), L.rpre.back(), L.d_tasks.p, td, c.tv, c.ma, c.mb, ws, c.s, lowp);
     c.timer.end();
   }
 }
 
-void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& pool_out) {
+void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& pool_out, DevBuf<float>& pool32_out) {
   const Tree& t = *c.t;
   hipStream_t s = c.s;
   // data layout in the pool
@@ -488,6 +515,11 @@ void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& poo
     DevBuf<double> ws(size_t(std::max<int64_t>(fh.ws_len, 1)));
     run_tasks(c, fh, nullptr, ws.p, true);
   }
+  if (c.lowp) {
+    if (pool32_out.n < size_t(std::max<int64_t>(pos, 1))) pool32_out.alloc(size_t(std::max<int64_t>(pos, 1)));
+    if (pos) launch_to_float(P, pool32_out.p, pos, s);
+    c.register_pool(P, pos, pool32_out.p);
+  }
   HM_CHECK_HIP(hipStreamSynchronize(s));
   c.st.t_host[6] += now_seconds() - tu;
   // device descriptors of these terms
@@ -561,6 +593,32 @@ void publish_terms(Ctx& c, const std::vector<int32_t>& which) {
   DevBuf<Term> src;
   src.upload(packed, c.s);
   launch_scatter_terms(ids.p, src.p, c.terms.p, int64_t(which.size()), c.s);
+  if (c.lowp) {
+    // the same terms over the float copies (TermT<float> has the layout of TermT<double>)
+    static_assert(sizeof(Term32) == sizeof(Term), "term layouts differ");
+    if (c.terms32.n < c.hterms.size()) c.terms32.alloc(c.hterms.size());
+    std::vector<Term32> p32(which.size());
+    for (size_t i = 0; i < which.size(); ++i) {
+      const Term& T = packed[i];
+      Term32& U = p32[i];
+      U.L = c.to32(T.L);
+      U.R = c.to32(T.R);
+      U.core = c.to32(T.core);
+      U.ldl = T.ldl;
+      U.ldr = T.ldr;
+      U.lrow0 = T.lrow0;
+      U.rrow0 = T.rrow0;
+      U.kl = T.kl;
+      U.kr = T.kr;
+      U.rtrans = T.rtrans;
+      U.pad = 0;
+    }
+    DevBuf<Term32> src32;
+    src32.upload(p32, c.s);
+    launch_scatter_terms(ids.p, reinterpret_cast<const Term*>(src32.p), reinterpret_cast<Term*>(c.terms32.p),
+                         int64_t(which.size()), c.s);
+    c.tv.terms32 = c.terms32.p;
+  }
   HM_CHECK_HIP(hipStreamSynchronize(c.s));
 }
 
@@ -762,7 +820,7 @@ void upload_chunk(Chunk& ch, hipStream_t s) {
 }
 
 // One application of every target's operator in the chunk (forward: S X, transposed: S^T X).
-void run_pass(Ctx& c, Chunk& ch, const std::vector<TDesc>& td, bool trans) {
+void run_pass(Ctx& c, Chunk& ch, const std::vector<TDesc>& td, bool trans, bool lowp = false) {
   hipStream_t s = c.s;
   ch.d_td.upload(td, s);  // synchronous: td is rewritten for the next pass
   const TDesc* dtd = ch.d_td.p;
@@ -782,31 +840,31 @@ void run_pass(Ctx& c, Chunk& ch, const std::vector<TDesc>& td, bool trans) {
       }
     }
   if (!trans) {
-    run_tasks(c, ch.t1f, dtd, ch.wsf.p, true);
-    run_tasks(c, ch.t2f, dtd, ch.wsf.p, true);
+    run_tasks(c, ch.t1f, dtd, ch.wsf.p, true, lowp);
+    run_tasks(c, ch.t2f, dtd, ch.wsf.p, true, lowp);
   } else {
-    run_tasks(c, ch.t1t, dtd, ch.wst.p, true);
-    run_tasks(c, ch.t2t, dtd, ch.wst.p, true);
+    run_tasks(c, ch.t1t, dtd, ch.wst.p, true, lowp);
+    run_tasks(c, ch.t2t, dtd, ch.wst.p, true, lowp);
   }
   if (!ch.term_items.empty()) {
     c.timer.begin(K_TERM);
-    launch_term_reduce(ch.d_terms.p, ch.term_items.size(), dtd, ch.d_info.p, c.tv, ch.vbuf.p, s);
+    launch_term_reduce(ch.d_terms.p, ch.term_items.size(), dtd, ch.d_info.p, c.tv, ch.vbuf.p, s, lowp);
     c.timer.end();
   }
   const size_t ng = trans ? ch.gt.size() : ch.gf.size();
   if (ng) {
     c.timer.begin(K_GATHER);
-    launch_gather_mfma(trans ? ch.d_gt.p : ch.d_gf.p, ng, dtd, ch.d_info.p, ch.d_pairs.p, c.tv, ch.vbuf.p, s);
+    launch_gather_mfma(trans ? ch.d_gt.p : ch.d_gf.p, ng, dtd, ch.d_info.p, ch.d_pairs.p, c.tv, ch.vbuf.p, s, lowp);
     c.timer.end();
   }
   if (!ch.small.empty()) {
     c.timer.begin(K_FUSED);
-    launch_fused_terms(ch.d_small.p, ch.small.size(), dtd, ch.d_info.p, ch.d_pairs.p, c.tv, s);
+    launch_fused_terms(ch.d_small.p, ch.small.size(), dtd, ch.d_info.p, ch.d_pairs.p, c.tv, s, lowp);
     c.timer.end();
   }
   if (!ch.small4.empty()) {
     c.timer.begin(K_FUSED4);
-    launch_fused_terms4(ch.d_small4.p, ch.small4.size(), dtd, ch.d_info.p, ch.d_pairs.p, c.tv, s);
+    launch_fused_terms4(ch.d_small4.p, ch.small4.size(), dtd, ch.d_info.p, ch.d_pairs.p, c.tv, s, lowp);
     c.timer.end();
   }
 }
@@ -908,7 +966,7 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
         }
         any = true;
       }
-      if (any) run_pass(c, ch, td, false);
+      if (any) run_pass(c, ch, td, false, c.lowp);
     }
   };
   auto project = [&](const std::vector<int>& r_from, const std::vector<int>& r_to) {
@@ -1118,6 +1176,19 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   c.dfs = dfs_order(*t);
   build_kpref(A, c.dfs, c.da, s);
   build_kpref(B, c.dfs, c.db, s);
+  c.lowp = opts.o.precision == HMAT_FP32_APPLY;
+  if (c.lowp) {
+    for (HMat* M : {A, B}) {
+      std::lock_guard<std::mutex> lk(M->mu32);
+      if (!M->pool32.p || M->pool32.n < size_t(std::max<int64_t>(M->pool_len, 1))) {
+        M->pool32.alloc(size_t(std::max<int64_t>(M->pool_len, 1)));
+        if (M->pool_len) launch_to_float(M->pool.p, M->pool32.p, M->pool_len, s);
+        HM_CHECK_HIP(hipStreamSynchronize(s));
+      }
+    }
+    c.register_pool(A->pool.p, A->pool_len, A->pool32.p);
+    c.register_pool(B->pool.p, B->pool_len, B->pool32.p);
+  }
   c.ma = c.da.view(A);
   c.mb = c.db.view(B);
   build_subsums(c, A, c.sa);
@@ -1317,7 +1388,7 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   DevBuf<double> global_pool;
   {
     double tc = now_seconds();
-    create_terms(c, gterms, global_pool);
+    create_terms(c, gterms, global_pool, c.gpool32);
     publish_terms(c, gterms);
     c.tv.terms = c.terms.p;
     c.st.t_restrict += now_seconds() - tc;
@@ -1356,7 +1427,7 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     }
     for (int k = 0; k < nbatch; ++k) {
       double tc = now_seconds();
-      create_terms(c, bterms[k], batch_pool);
+      create_terms(c, bterms[k], batch_pool, c.bpool32);
       publish_terms(c, bterms[k]);
       c.tv.terms = c.terms.p;
       c.st.t_restrict += now_seconds() - tc;
@@ -1463,7 +1534,9 @@ hmat_status multiply_batched(HMat* const* A, HMat* const* B, int32_t count, doub
   std::vector<hmat_stats> pst(size_t(std::max(count, 1)));
   std::vector<hmat_status> pstat(size_t(std::max(count, 1)), HMAT_OK);
   std::vector<std::string> perr(size_t(std::max(count, 1)));
-  // products [lo, hi) on S streams; returns the wall time
+  // products idx[lo, hi) on S streams; returns the wall time
+  std::vector<int32_t> idx(size_t(std::max(count, 1)));
+  for (int32_t i = 0; i < count; ++i) idx[i] = i;
   auto run_range = [&](int32_t lo, int32_t hi, int S) {
     std::atomic<int32_t> next{lo};
     std::vector<std::thread> th;
@@ -1476,8 +1549,9 @@ hmat_status multiply_batched(HMat* const* A, HMat* const* B, int32_t count, doub
           s = nullptr;
         }
         for (;;) {
-          const int32_t i = next.fetch_add(1);
-          if (i >= hi) break;
+          const int32_t k = next.fetch_add(1);
+          if (k >= hi) break;
+          const int32_t i = idx[k];
           if (!s) {
             pstat[i] = HMAT_ERR_DEVICE;
             perr[i] = "stream creation failed";
@@ -1543,6 +1617,19 @@ hmat_status multiply_batched(HMat* const* A, HMat* const* B, int32_t count, doub
   }
   if (S <= 0) S = 1;
   if (done < count) run_range(done, count, std::min<int>(S, count - done));
+  // products that ran out of device memory next to others are run again alone
+  {
+    int32_t nre = 0;
+    for (int32_t i = 0; i < count; ++i)
+      if (pstat[i] == HMAT_ERR_OOM) {
+        if (C[i]) hmat_release(C[i]);
+        C[i] = nullptr;
+        pst[i] = hmat_stats{};
+        perr[i].clear();
+        idx[nre++] = i;
+      }
+    if (nre) run_range(0, nre, 1);
+  }
   hmat_status worst = HMAT_OK;
   std::string first_err;
   hmat_stats tot{};

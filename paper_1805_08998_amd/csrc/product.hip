@@ -63,6 +63,7 @@ __device__ __forceinline__ dbl4 mfma4(double a, double b, dbl4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+template <class TS>
 __global__ void __launch_bounds__(64) k_fused_terms(const int32_t* __restrict__ tlist, const TDesc* __restrict__ td,
                                                    const TInfo* __restrict__ ti, const HPair* __restrict__ hp,
                                                    TreeView tv) {
@@ -94,11 +95,11 @@ __global__ void __launch_bounds__(64) k_fused_terms(const int32_t* __restrict__ 
   for (int q = 0; q < 4; ++q) y[q] = dbl4{0.0, 0.0, 0.0, 0.0};
   for (int a = tb; a >= 0; a = tv.b_parent[a]) {
     for (int it = tv.group_ptr[a]; it < tv.group_ptr[a + 1]; ++it) {
-      const Term T = tv.terms[it];
+      const TermT<TS> T = tree_terms<TS>(tv)[it];
       // reduction operand M (rows = input cluster), expansion operand P (rows = output cluster)
-      const double* M;
+      const TS* M;
       int ldm, mtr, kin;
-      const double* P;
+      const TS* P;
       int ldp, ptr, kp;
       if (!d.trans) {
         const int rr = in0 - T.rrow0;
@@ -217,6 +218,7 @@ __device__ __forceinline__ int find_owner(const int64_t* __restrict__ pre, int n
   return lo;
 }
 
+template <class TS>
 __global__ void __launch_bounds__(64) k_leaf_reduce(const int64_t* __restrict__ pre, int ntask, int64_t g0,
                                                    const Task* __restrict__ tasks, const TDesc* __restrict__ td,
                                                    const int32_t* __restrict__ dfs_block, TreeView tv, MatView ma,
@@ -237,8 +239,8 @@ __global__ void __launch_bounds__(64) k_leaf_reduce(const int64_t* __restrict__ 
   const int qt = tv.b_tau[tk.q], qs = tv.b_sigma[tk.q];
   const int bt = tv.b_tau[b], bs = tv.b_sigma[b];
   const int m = tv.c_size[bt], n = tv.c_size[bs];
-  const double* base = mv.pool + mv.off[b];
-  const double* M;
+  const TS* base = mat_pool<TS>(mv) + mv.off[b];
+  const TS* M;
   int rows, ro, ldm;
   if (!tk.trans) {
     M = base + int64_t(kr) * m;
@@ -275,6 +277,7 @@ __global__ void __launch_bounds__(64) k_leaf_reduce(const int64_t* __restrict__ 
   }
 }
 
+template <class TS>
 __global__ void __launch_bounds__(64) k_subtree_expand(const int64_t* __restrict__ pre, int ntask, int64_t g0,
                                                       const Task* __restrict__ tasks, const TDesc* __restrict__ td,
                                                       TreeView tv, MatView ma, MatView mb,
@@ -319,13 +322,13 @@ __global__ void __launch_bounds__(64) k_subtree_expand(const int64_t* __restrict
       if (o0 >= in1) break;
       if (o1 > in1) continue;
       const int m = tv.c_size[tv.b_tau[b]], n = tv.c_size[tv.b_sigma[b]];
-      const double* base = mv.pool + mv.off[b];
+      const TS* base = mat_pool<TS>(mv) + mv.off[b];
       const int roff = row_lo - tv.c_begin[a];  // first output row inside the leaf's rows
       if (tv.b_kind[b] == KIND_F) {
         const int k = mv.rank[b];
         if (k == 0) continue;
         const double* Tm = ws + tk.tws + (mv.kpref[tv.b_dfs[b]] - mv.kpref[tk.lo]) * PW;
-        const double* P = tk.trans ? base + int64_t(k) * m : base;
+        const TS* P = tk.trans ? base + int64_t(k) * m : base;
         const int ldp = tk.trans ? n : m;
         const int ks = (k + 3) >> 2;
         for (int s = 0; s < ks; ++s) {
@@ -377,16 +380,17 @@ __global__ void __launch_bounds__(64) k_subtree_expand(const int64_t* __restrict
 
 // Large targets: per (target, term) V = core (M^T X) on MFMA (M = R forward, L
 // transposed), written to the target's slot; the expansion is k_gather_mfma.
+template <class TS>
 __global__ void __launch_bounds__(64) k_term_reduce(const TermItem* __restrict__ items, const TDesc* __restrict__ td,
                                                    const TInfo* __restrict__ ti, TreeView tv,
                                                    double* __restrict__ vbuf) {
   const TermItem it = items[blockIdx.x];
   const TDesc d = td[it.t];
   if (d.w == 0) return;
-  const Term T = tv.terms[it.term];
+  const TermT<TS> T = tree_terms<TS>(tv)[it.term];
   const int tb = ti[it.t].block;
   const int tau = tv.b_tau[tb], sig = tv.b_sigma[tb];
-  const double* M;
+  const TS* M;
   int ldm, mtr, nin, kin, kout;
   if (!d.trans) {
     const int rr = tv.c_begin[sig] - T.rrow0;
@@ -467,6 +471,7 @@ __global__ void __launch_bounds__(64) k_term_reduce(const TermItem* __restrict__
   }
 }
 
+template <class TS>
 __global__ void __launch_bounds__(64) k_gather_mfma(const RowItem* __restrict__ items, const TDesc* __restrict__ td,
                                                    const TInfo* __restrict__ ti, const HPair* __restrict__ hp,
                                                    TreeView tv, const double* __restrict__ vbuf) {
@@ -488,12 +493,12 @@ __global__ void __launch_bounds__(64) k_gather_mfma(const RowItem* __restrict__ 
   int64_t voff = inf.vbase;
   for (int a = tb; a >= 0; a = tv.b_parent[a]) {
     for (int i = tv.group_ptr[a]; i < tv.group_ptr[a + 1]; ++i) {
-      const Term T = tv.terms[i];
+      const TermT<TS> T = tree_terms<TS>(tv)[i];
       const int kout = d.trans ? T.kr : T.kl;
       const double* V = vbuf + voff;
       voff += int64_t(T.kl > T.kr ? T.kl : T.kr) * PW;
       if (kout == 0) continue;
-      const double* P;
+      const TS* P;
       int ldp, ptr;
       int64_t r0;
       if (!d.trans) {
@@ -542,44 +547,53 @@ __global__ void __launch_bounds__(64) k_gather_mfma(const RowItem* __restrict__ 
 }
 
 void launch_term_reduce(const TermItem* items, size_t n, const TDesc* td, const TInfo* ti, const TreeView& tv,
-                        double* vbuf, hipStream_t s) {
+                        double* vbuf, hipStream_t s, bool lowp) {
   const size_t maxg = size_t(1) << 30;
   for (size_t b = 0; b < n; b += maxg) {
     unsigned cnt = unsigned(std::min(maxg, n - b));
-    hipLaunchKernelGGL(k_term_reduce, dim3(cnt), dim3(64), 0, s, items + b, td, ti, tv, vbuf);
+    if (lowp) hipLaunchKernelGGL(k_term_reduce<float>, dim3(cnt), dim3(64), 0, s, items + b, td, ti, tv, vbuf);
+    else hipLaunchKernelGGL(k_term_reduce<double>, dim3(cnt), dim3(64), 0, s, items + b, td, ti, tv, vbuf);
     HM_CHECK_HIP(hipGetLastError());
   }
 }
 
 void launch_gather_mfma(const RowItem* items, size_t n, const TDesc* td, const TInfo* ti, const HPair* hp,
-                        const TreeView& tv, const double* vbuf, hipStream_t s) {
+                        const TreeView& tv, const double* vbuf, hipStream_t s, bool lowp) {
   const size_t maxg = size_t(1) << 30;
   for (size_t b = 0; b < n; b += maxg) {
     unsigned cnt = unsigned(std::min(maxg, n - b));
-    hipLaunchKernelGGL(k_gather_mfma, dim3(cnt), dim3(64), 0, s, items + b, td, ti, hp, tv, vbuf);
+    if (lowp) hipLaunchKernelGGL(k_gather_mfma<float>, dim3(cnt), dim3(64), 0, s, items + b, td, ti, hp, tv, vbuf);
+    else hipLaunchKernelGGL(k_gather_mfma<double>, dim3(cnt), dim3(64), 0, s, items + b, td, ti, hp, tv, vbuf);
     HM_CHECK_HIP(hipGetLastError());
   }
 }
 
 void launch_leaf_reduce(const int64_t* pre, int ntask, int64_t nitems, const Task* tasks, const TDesc* td,
                         const int32_t* dfs_block, const TreeView& tv, const MatView& ma, const MatView& mb,
-                        double* ws, hipStream_t s) {
+                        double* ws, hipStream_t s, bool lowp) {
   const int64_t maxg = int64_t(1) << 30;
   for (int64_t b = 0; b < nitems; b += maxg) {
     unsigned cnt = unsigned(std::min(maxg, nitems - b));
-    hipLaunchKernelGGL(k_leaf_reduce, dim3(cnt), dim3(64), 0, s, pre, ntask, b, tasks, td, dfs_block, tv, ma, mb,
-                       ws);
+    if (lowp)
+      hipLaunchKernelGGL(k_leaf_reduce<float>, dim3(cnt), dim3(64), 0, s, pre, ntask, b, tasks, td, dfs_block, tv, ma,
+                         mb, ws);
+    else
+      hipLaunchKernelGGL(k_leaf_reduce<double>, dim3(cnt), dim3(64), 0, s, pre, ntask, b, tasks, td, dfs_block, tv,
+                         ma, mb, ws);
     HM_CHECK_HIP(hipGetLastError());
   }
 }
 
 void launch_subtree_expand(const int64_t* pre, int ntask, int64_t nitems, const Task* tasks, const TDesc* td,
                            const TreeView& tv, const MatView& ma, const MatView& mb, const double* ws,
-                           hipStream_t s) {
+                           hipStream_t s, bool lowp) {
   const int64_t maxg = int64_t(1) << 30;
   for (int64_t b = 0; b < nitems; b += maxg) {
     unsigned cnt = unsigned(std::min(maxg, nitems - b));
-    hipLaunchKernelGGL(k_subtree_expand, dim3(cnt), dim3(64), 0, s, pre, ntask, b, tasks, td, tv, ma, mb, ws);
+    if (lowp)
+      hipLaunchKernelGGL(k_subtree_expand<float>, dim3(cnt), dim3(64), 0, s, pre, ntask, b, tasks, td, tv, ma, mb, ws);
+    else
+      hipLaunchKernelGGL(k_subtree_expand<double>, dim3(cnt), dim3(64), 0, s, pre, ntask, b, tasks, td, tv, ma, mb, ws);
     HM_CHECK_HIP(hipGetLastError());
   }
 }
@@ -587,6 +601,7 @@ void launch_subtree_expand(const int64_t* pre, int ntask, int64_t nitems, const 
 // Four waves per target for clusters of up to 256 rows: wave q reduces input rows
 // [64q, 64q + 64) and expands output rows [64q, 64q + 64); the partial products
 // M^T X of the four waves are summed through double-buffered LDS (one barrier per term).
+template <class TS>
 __global__ void __launch_bounds__(256) k_fused_terms4(const int32_t* __restrict__ tlist, const TDesc* __restrict__ td,
                                                      const TInfo* __restrict__ ti, const HPair* __restrict__ hp,
                                                      TreeView tv) {
@@ -624,10 +639,10 @@ __global__ void __launch_bounds__(256) k_fused_terms4(const int32_t* __restrict_
   int buf = 0;
   for (int a = tb; a >= 0; a = tv.b_parent[a]) {
     for (int it = tv.group_ptr[a]; it < tv.group_ptr[a + 1]; ++it) {
-      const Term T = tv.terms[it];
-      const double* M;
+      const TermT<TS> T = tree_terms<TS>(tv)[it];
+      const TS* M;
       int ldm, mtr, kin;
-      const double* P;
+      const TS* P;
       int ldp, ptr, kp;
       if (!d.trans) {
         const int rr = in0 - T.rrow0;
@@ -750,21 +765,23 @@ __global__ void __launch_bounds__(256) k_fused_terms4(const int32_t* __restrict_
 }
 
 void launch_fused_terms4(const int32_t* tlist, size_t n, const TDesc* td, const TInfo* ti, const HPair* hp,
-                         const TreeView& tv, hipStream_t s) {
+                         const TreeView& tv, hipStream_t s, bool lowp) {
   const size_t maxg = size_t(1) << 30;
   for (size_t b = 0; b < n; b += maxg) {
     unsigned cnt = unsigned(std::min(maxg, n - b));
-    hipLaunchKernelGGL(k_fused_terms4, dim3(cnt), dim3(256), 0, s, tlist + b, td, ti, hp, tv);
+    if (lowp) hipLaunchKernelGGL(k_fused_terms4<float>, dim3(cnt), dim3(256), 0, s, tlist + b, td, ti, hp, tv);
+    else hipLaunchKernelGGL(k_fused_terms4<double>, dim3(cnt), dim3(256), 0, s, tlist + b, td, ti, hp, tv);
     HM_CHECK_HIP(hipGetLastError());
   }
 }
 
 void launch_fused_terms(const int32_t* tlist, size_t n, const TDesc* td, const TInfo* ti, const HPair* hp,
-                        const TreeView& tv, hipStream_t s) {
+                        const TreeView& tv, hipStream_t s, bool lowp) {
   const size_t maxg = size_t(1) << 30;
   for (size_t b = 0; b < n; b += maxg) {
     unsigned cnt = unsigned(std::min(maxg, n - b));
-    hipLaunchKernelGGL(k_fused_terms, dim3(cnt), dim3(64), 0, s, tlist + b, td, ti, hp, tv);
+    if (lowp) hipLaunchKernelGGL(k_fused_terms<float>, dim3(cnt), dim3(64), 0, s, tlist + b, td, ti, hp, tv);
+    else hipLaunchKernelGGL(k_fused_terms<double>, dim3(cnt), dim3(64), 0, s, tlist + b, td, ti, hp, tv);
     HM_CHECK_HIP(hipGetLastError());
   }
 }
@@ -772,6 +789,20 @@ void launch_fused_terms(const int32_t* tlist, size_t n, const TDesc* td, const T
 }  // namespace hm
 
 namespace hm {
+
+__global__ void k_to_float(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = float(src[i]);
+}
+
+void launch_to_float(const double* src, float* dst, int64_t n, hipStream_t s) {
+  const int64_t per = int64_t(256) * (int64_t(1) << 30);
+  for (int64_t b = 0; b < n; b += per) {
+    const int64_t cnt = std::min(per, n - b);
+    hipLaunchKernelGGL(k_to_float, dim3(unsigned((cnt + 255) / 256)), dim3(256), 0, s, src + b, dst + b, cnt);
+    HM_CHECK_HIP(hipGetLastError());
+  }
+}
 
 __global__ void k_scatter_terms(const int32_t* __restrict__ ids, const Term* __restrict__ src, Term* __restrict__ dst,
                                 int64_t n) {

@@ -11,21 +11,26 @@ constexpr int PW = 16;  // columns per apply pass (wider passes are split)
 // One low-rank term of a sum-expression, L * core * R^T (Def. 3.1), stored
 // through views into the factor pools. Restriction to a sub-block (Algorithm 3)
 // is an index shift: row position p of the target maps to panel row p - lrow0.
-struct Term {
-  const double* L;     // element (i, c) at L[i + c * ldl]
-  const double* R;     // rtrans == 0: (j, c) at R[j + c * ldr]; rtrans == 1: at R[c + j * ldr]
-  const double* core;  // kl x kr column-major (ld kl), or null when kl == kr and the core is I
+// T is the storage type of the panels (double, or float for the fp32 copies).
+template <class T>
+struct TermT {
+  const T* L;     // element (i, c) at L[i + c * ldl]
+  const T* R;     // rtrans == 0: (j, c) at R[j + c * ldr]; rtrans == 1: at R[c + j * ldr]
+  const T* core;  // kl x kr column-major (ld kl), or null when kl == kr and the core is I
   int32_t ldl, ldr;
   int32_t lrow0, rrow0;
   int32_t kl, kr;
   int32_t rtrans, pad;
 };
+using Term = TermT<double>;
+using Term32 = TermT<float>;
 
 struct MatView {
   const double* pool;
   const int32_t* rank;   // per block
   const int64_t* off;    // per block, element offset of the leaf data in pool
   const int64_t* kpref;  // per depth-first leaf index: prefix sum of farfield ranks
+  const float* pool32;   // float copy of pool (mixed precision), else null
 };
 
 struct TreeView {
@@ -45,7 +50,17 @@ struct TreeView {
   const int32_t* group_ptr;  // terms created at each block
   const Term* terms;
   const int32_t* c_lc_begin;  // first index into leaf_clusters of each cluster
+  const Term32* terms32;      // the same terms over the float panel copies (mixed precision)
 };
+
+// Storage-type views: the kernels are instantiated for double panels and for
+// their float copies; arithmetic is float64 in both.
+template <class T> __host__ __device__ inline const T* mat_pool(const MatView& m);
+template <> __host__ __device__ inline const double* mat_pool<double>(const MatView& m) { return m.pool; }
+template <> __host__ __device__ inline const float* mat_pool<float>(const MatView& m) { return m.pool32; }
+template <class T> __host__ __device__ inline const TermT<T>* tree_terms(const TreeView& v);
+template <> __host__ __device__ inline const Term* tree_terms<double>(const TreeView& v) { return v.terms; }
+template <> __host__ __device__ inline const Term32* tree_terms<float>(const TreeView& v) { return v.terms32; }
 
 // Pass descriptor of one target: the target's operator is applied to X
 // (forward: S X with X rows = sigma, output rows = tau; transposed: S^T X with
