@@ -185,6 +185,10 @@ typedef struct {
   /* hmat_multiply_batched: products in flight at once (chosen or autotuned) */
   int32_t streams_used;
   int32_t pad_s;
+  /* nearfield targets evaluated by the direct kernel, and seconds spent on the
+   * other nearfield targets (identity panels) */
+  int64_t n_near_direct;
+  double t_near_panels;
 } hmat_stats;
 
 /* Kernel families of hmat_stats.kern_* */
@@ -195,7 +199,8 @@ enum {
   HMAT_KERN_GATHER = 3,        /* per target: sum of L V over its terms and pair results */
   HMAT_KERN_COMPRESS = 4,      /* orthogonalisation, probe residual, core SVD, output */
   HMAT_KERN_FUSED_TERMS = 5,   /* fused term reduce + expand, targets of <= 64 rows/columns */
-  HMAT_KERN_FUSED_TERMS4 = 6   /* the same with four waves, targets of <= 256 rows/columns */
+  HMAT_KERN_FUSED_TERMS4 = 6,  /* the same with four waves, targets of <= 256 rows/columns */
+  HMAT_KERN_NEAR_DIRECT = 7    /* nearfield targets of <= 64 x 64 with dense pairs, all columns at once */
 };
 
 typedef struct {
@@ -214,7 +219,7 @@ typedef struct {
   hmat_stats* stats;   /* optional output */
   int64_t workspace_limit;     /* bytes of device workspace per subtree batch (0 = auto) */
   int32_t streams;     /* hmat_multiply_batched: products in flight at once, each on its own
-                          stream and host thread (0 = autotuned, default) */
+                          stream and host thread, 1..4 (0 = autotuned, default) */
   int32_t pad;
 } hmat_opts;
 
@@ -283,7 +288,7 @@ hmat_status hmat_multiply(hmat A, hmat B, double eps, const hmat_opts* opts, hma
  * Products run concurrently: opts->streams host threads, each with its own
  * HIP stream (created and destroyed inside the call; opts->stream is not
  * used), take products in index order. With streams = 0 the count is
- * autotuned: the first products are run with 1, 2, 4 and 8 streams (2 x
+ * autotuned: the first products are run with 1, 2 and 4 streams (2 x
  * streams products each), the rate (algorithmic flops / wall time) of each
  * trial is compared, the best count runs the rest and is remembered for
  * later batches of the same size class (rounded mean log2 n). If

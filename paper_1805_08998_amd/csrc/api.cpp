@@ -28,15 +28,18 @@ static void (*g_free)(void*, void*) = nullptr;
 static void* g_ctx = nullptr;
 
 // Caching of device blocks when no allocator hook is set: a freed block keeps
-// its (rounded) size class and an event recorded on the library's current
-// stream; it is handed out again only once that event has completed, so work
-// still queued on the old buffer can never see it reused. On allocation
+// its (rounded) size class, the stream current at the free and an event
+// recorded there. It is handed out again to work on the same stream at once
+// (stream order puts the new use after the old one), to other streams only once
+// the event has completed, so work still queued on the old buffer can never
+// see it reused. On allocation
 // failure idle cached blocks are freed, largest first, and the allocation
 // retried.
 static thread_local hipStream_t g_stream = 0;  // per host thread (concurrent products)
 struct CachedBlock {
   void* p;
   hipEvent_t ev;
+  hipStream_t stream;  // stream current when it was freed: work on it is ordered after the free
 };
 static std::map<std::pair<int, size_t>, std::vector<CachedBlock>> g_cache;
 static std::unordered_map<void*, std::pair<int, size_t>> g_live;
@@ -131,7 +134,7 @@ void* dev_alloc(size_t bytes) {
          it != g_cache.end() && it->first.first == dev && it->first.second <= rs + rs / 2; ++it) {
       auto& v = it->second;
       for (size_t i = 0; i < v.size(); ++i)
-        if (hipEventQuery(v[i].ev) == hipSuccess) {
+        if (v[i].stream == g_stream || hipEventQuery(v[i].ev) == hipSuccess) {
           p = v[i].p;
           const size_t got = it->first.second;
           (void)hipEventDestroy(v[i].ev);
@@ -190,7 +193,7 @@ void dev_free(void* p) {
       (void)hipFree(p);
       return;
     }
-    g_cache[key].push_back({p, ev});
+    g_cache[key].push_back({p, ev, g_stream});
     g_cached_bytes += key.second;
     if (g_cached_bytes > cache_limit()) victims = take_blocks_locked(g_cached_bytes - cache_limit() / 2);
   }
@@ -255,7 +258,7 @@ Opts resolve_opts(const hmat_opts* o) {
              "unknown rank mode");
   HM_REQUIRE(r.o.rank_mode != HMAT_RANK_PREDICT || r.o.rank_model != nullptr, HMAT_ERR_ARG,
              "HMAT_RANK_PREDICT needs opts.rank_model");
-  HM_REQUIRE(r.o.streams >= 0 && r.o.streams <= 16, HMAT_ERR_ARG, "streams must be in [0, 16]");
+  HM_REQUIRE(r.o.streams >= 0 && r.o.streams <= 4, HMAT_ERR_ARG, "streams must be in [0, 4]");
   return r;
 }
 

@@ -42,6 +42,9 @@ void launch_scatter_terms(const int32_t* ids, const Term* src, Term* dst, int64_
 void launch_fused_terms4(const int32_t* tlist, size_t n, const TDesc* td, const TInfo* ti, const HPair* hp,
                          const TreeView& tv, hipStream_t s, bool lowp);
 void launch_to_float(const double* src, float* dst, int64_t n, hipStream_t s);
+void launch_near_direct(const int32_t* items, int64_t nitems, const int32_t* blocks, const int64_t* coff,
+                        const int32_t* pptr, const int32_t* pairs, const TreeView& tv, const MatView& ma,
+                        const MatView& mb, double* cpool, hipStream_t s);
 
 namespace {
 
@@ -113,7 +116,7 @@ void build_kpref(const HMat* M, const DfsInfo& d, DevMat& dm, hipStream_t s) {
 struct Coef {
   double a = 0, b = 0, f = 0;
 };
-enum { K_TERM = 0, K_LEAF = 1, K_EXPAND = 2, K_GATHER = 3, K_COMPRESS = 4, K_FUSED = 5, K_FUSED4 = 6 };
+enum { K_TERM = 0, K_LEAF = 1, K_EXPAND = 2, K_GATHER = 3, K_COMPRESS = 4, K_FUSED = 5, K_FUSED4 = 6, K_NEAR = 7 };
 // targets whose clusters both have at most FUSED_MAX (one wave) or FUSED4_MAX (four
 // waves) rows use the fused MFMA kernels
 constexpr int FUSED_MAX = 64;
@@ -647,7 +650,14 @@ struct Chunk {
   std::vector<uint8_t> is_small;
   DevBuf<int32_t> d_small, d_small4;
   std::vector<float> feats;  // HMAT_N_FEATURES per target (farfield chunks, when needed)
+  // nearfield chunks: targets of at most NEAR_MAX rows and columns are evaluated by the
+  // direct kernel (terms and dense x dense pairs); their other pairs stay in `pairs`
+  bool near = false;
+  std::vector<uint8_t> direct;
+  std::vector<int32_t> dpptr, dpairs;  // per direct target (chunk order): dense pairs (A block, B block)
 };
+
+constexpr int NEAR_MAX = 256;
 
 // Features of a farfield target for the rank predictor: level, log diam tau,
 // log diam sigma, log dist(tau, sigma), log(1 + sum of the ranks of the
@@ -705,11 +715,16 @@ void build_chunk(const Ctx& c, Chunk& ch, bool features) {
   for (int k = 0; k < 4; ++k)
     for (int d = 0; d < 2; ++d) ch.coef[k][d].assign(nt, Coef{});
   ch.is_small.assign(nt, 0);
+  ch.direct.assign(nt, 0);
+  ch.dpptr.assign(1, 0);
+  ch.dpairs.clear();
   for (int i = 0; i < nt; ++i) {
     const int32_t b = ch.blocks[i];
     TInfo& ti = ch.info[i];
     ti.block = b;
     ti.vbase = ch.vlen;
+    const bool direct = ch.near && c.m_of(b) <= NEAR_MAX && c.n_of(b) <= NEAR_MAX;
+    ch.direct[i] = direct;
     const double mt = t.c_size[t.b_tau[b]], nt_ = t.c_size[t.b_sigma[b]];
     const bool small1 = mt <= FUSED_MAX && nt_ <= FUSED_MAX;
     const bool small = mt <= FUSED4_MAX && nt_ <= FUSED4_MAX;
@@ -755,6 +770,11 @@ void build_chunk(const Ctx& c, Chunk& ch, bool features) {
     for (int32_t j = c.hptr[b]; j < c.hptr[b + 1]; ++j) {
       const int32_t rho = c.hrho[3 * j], qa = c.hrho[3 * j + 1], qb = c.hrho[3 * j + 2];
       if (qa < 0 || qb < 0) throw Error(HMAT_ERR_INTERNAL, "pair blocks missing");
+      if (direct && t.b_kind[qa] == KIND_N && t.b_kind[qb] == KIND_N) {  // done by the direct kernel
+        ch.dpairs.push_back(qa);
+        ch.dpairs.push_back(qb);
+        continue;
+      }
       subtree_coef(c, 1, qb, 0, ch.coef[K_LEAF][0][i], ch.coef[K_EXPAND][0][i]);
       subtree_coef(c, 0, qa, 0, ch.coef[K_LEAF][0][i], ch.coef[K_EXPAND][0][i]);
       subtree_coef(c, 0, qa, 1, ch.coef[K_LEAF][1][i], ch.coef[K_EXPAND][1][i]);
@@ -788,6 +808,10 @@ void build_chunk(const Ctx& c, Chunk& ch, bool features) {
       stage(ch.t2t, ch.tws_t, 1, qb, 1, off1, off2, n);
     }
     ti.hp_end = int32_t(ch.pairs.size());
+    if (direct) {
+      ch.dpptr.push_back(int32_t(ch.dpairs.size() / 2));
+      for (int d = 0; d < 2; ++d) ch.coef[K_TERM][d][i] = ch.coef[K_GATHER][d][i] = Coef{};  // terms: direct kernel
+    }
     if (!small) {
       add_subtree_rows(t, i, tau, ch.gf);
       add_subtree_rows(t, i, sig, ch.gt);
@@ -1117,8 +1141,66 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
 void evaluate_chunk(Ctx& c, Chunk& ch, double* cpool, const std::vector<int64_t>& coff) {
   const Tree& t = *c.t;
   const int nt = int(ch.blocks.size());
+  // direct kernel: terms and dense x dense pairs of the targets of at most NEAR_MAX x NEAR_MAX,
+  // one work item per 64 x 64 sub-block
+  std::vector<int32_t> dblk, items;
+  std::vector<int64_t> dco;
+  for (int i = 0; i < nt; ++i) {
+    if (!ch.direct[i]) continue;
+    const int32_t b = ch.blocks[i];
+    const int m = c.m_of(b), n = c.n_of(b);
+    const int k = int32_t(dblk.size());
+    for (int rb = 0; rb < (m + 63) / 64; ++rb)
+      for (int cb = 0; cb < (n + 63) / 64; ++cb) {
+        items.push_back(k);
+        items.push_back((rb << 16) | cb);
+      }
+    double by = 8.0 * m * n, fl = 0.0;
+    for (int32_t a = b; a >= 0; a = t.b_parent[a])
+      for (int32_t j = c.group_ptr_h[a]; j < c.group_ptr_h[a + 1]; ++j) {
+        const SymTerm& sy = c.sym[j];
+        const double core = sy.type == T_FF ? double(sy.kl) * sy.kr : 0.0;
+        by += 8.0 * (double(m) * sy.kl + double(n) * sy.kr + core);
+        fl += 2.0 * n * (core + double(m) * sy.kl);
+      }
+    for (int32_t p = ch.dpptr[k]; p < ch.dpptr[k + 1]; ++p) {
+      const double nr = t.c_size[t.b_sigma[ch.dpairs[2 * p]]];
+      by += 8.0 * (m * nr + nr * n);
+      fl += 2.0 * m * nr * n;
+    }
+    dblk.push_back(b);
+    dco.push_back(coff[i]);
+    c.st.kern_bytes[K_NEAR] += by;
+    c.st.kern_flops[K_NEAR] += fl;
+    c.alg_bytes += by;
+    c.alg_flops += fl;
+  }
+  c.st.n_near_direct += int64_t(dblk.size());
+  if (!dblk.empty()) {
+    DevBuf<int32_t> d_items, d_blk, d_pptr, d_prs;
+    DevBuf<int64_t> d_co;
+    d_items.upload(items, c.s);
+    d_blk.upload(dblk, c.s);
+    d_co.upload(dco, c.s);
+    d_pptr.upload(ch.dpptr, c.s);
+    std::vector<int32_t> prs = ch.dpairs;
+    if (prs.empty()) prs.push_back(0);
+    d_prs.upload(prs, c.s);
+    c.timer.begin(K_NEAR);
+    launch_near_direct(d_items.p, int64_t(items.size() / 2), d_blk.p, d_co.p, d_pptr.p, d_prs.p, c.tv, c.ma, c.mb,
+                       cpool, c.s);
+    c.timer.end();
+    HM_CHECK_HIP(hipStreamSynchronize(c.s));  // the small device arrays above are freed on return
+  }
+  // identity panels, PW columns at a time: whole targets beyond NEAR_MAX, and the pairs
+  // with a subdivided factor of direct targets (added to what the direct kernel wrote)
+  const double tp0 = now_seconds();
   int maxn = 0;
-  for (int32_t b : ch.blocks) maxn = std::max(maxn, c.n_of(b));
+  std::vector<uint8_t> panel(nt, 0);
+  for (int i = 0; i < nt; ++i) {
+    panel[i] = !ch.direct[i] || ch.info[i].hp_end > ch.info[i].hp_begin;
+    if (panel[i]) maxn = std::max(maxn, c.n_of(ch.blocks[i]));
+  }
   std::vector<TDesc> td(nt);
   for (int j0 = 0; j0 < maxn; j0 += PW) {
     for (int i = 0; i < nt; ++i) {
@@ -1126,7 +1208,7 @@ void evaluate_chunk(Ctx& c, Chunk& ch, double* cpool, const std::vector<int64_t>
       std::memset(&d, 0, sizeof(d));
       const int32_t b = ch.blocks[i];
       const int n = c.n_of(b), m = c.m_of(b);
-      if (j0 >= n) continue;
+      if (!panel[i] || j0 >= n) continue;
       d.w = std::min(PW, n - j0);
       d.trans = 0;
       d.xident = 1;
@@ -1135,19 +1217,21 @@ void evaluate_chunk(Ctx& c, Chunk& ch, double* cpool, const std::vector<int64_t>
       d.Y = cpool + coff[i] + int64_t(j0) * m;
       d.ldy = m;
       d.split = d.w;
+      d.accum = ch.direct[i];
     }
     run_pass(c, ch, td, false);
   }
   for (int i = 0; i < nt; ++i) {
+    if (!panel[i]) continue;
     const double w = c.n_of(ch.blocks[i]);
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 4; ++k) {  // term coefficients of direct targets are zero
       const Coef& cf = ch.coef[k][0][i];
       c.alg_bytes += cf.a + cf.b * w;
       c.alg_flops += cf.f * w;
     }
   }
   HM_CHECK_HIP(hipStreamSynchronize(c.s));
-  (void)t;
+  c.st.t_near_panels += now_seconds() - tp0;
 }
 
 }  // namespace
@@ -1333,6 +1417,7 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     auto launch_build = [&](size_t k) {
       auto ch = std::make_unique<Chunk>();
       ch->blocks = jobs[k].blocks;
+      ch->near = !jobs[k].far;
       next = std::async(std::launch::async, build, std::move(ch), jobs[k].far && (predict || collect));
     };
     if (!jobs.empty()) launch_build(0);
@@ -1519,6 +1604,8 @@ void add_stats(hmat_stats& a, const hmat_stats& b) {
   a.n_malloc += b.n_malloc;
   a.n_cache_release += b.n_cache_release;
   a.target_passes += b.target_passes;
+  a.n_near_direct += b.n_near_direct;
+  a.t_near_panels += b.t_near_panels;
 }
 }  // namespace
 
@@ -1591,11 +1678,11 @@ hmat_status multiply_batched(HMat* const* A, HMat* const* B, int32_t count, doub
       if (it != g_tuned_streams.end()) S = it->second;
     }
     if (S <= 0) {
-      // trials: 2 x S products each with S = 1, 2, 4, 8; the best rate runs the rest
+      // trials: 2 x S products each with S = 1, 2, 4; the best rate runs the rest
       double best = -1.0;
       int best_s = 1;
       bool complete = true;
-      for (int cand : {1, 2, 4, 8}) {
+      for (int cand : {1, 2, 4}) {
         const int32_t take = std::min<int32_t>(2 * cand, count - done);
         if (take < cand) {
           complete = false;

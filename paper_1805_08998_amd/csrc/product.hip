@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(64) k_fused_terms(const int32_t* __restrict__ 
   dbl4 y[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) y[q] = dbl4{0.0, 0.0, 0.0, 0.0};
-  for (int a = tb; a >= 0; a = tv.b_parent[a]) {
+  for (int a = d.accum ? -1 : tb; a >= 0; a = tv.b_parent[a]) {
     for (int it = tv.group_ptr[a]; it < tv.group_ptr[a + 1]; ++it) {
       const TermT<TS> T = tree_terms<TS>(tv)[it];
       // reduction operand M (rows = input cluster), expansion operand P (rows = output cluster)
@@ -195,9 +195,9 @@ __global__ void __launch_bounds__(64) k_fused_terms(const int32_t* __restrict__ 
     for (int v = 0; v < 4; ++v) {
       const int row = 16 * tile + lk + 4 * v;
       if (tile < ntile && row < nout && li < w) {
-        double val = y[tile][v];
-        for (int j = inf.hp_begin; j < inf.hp_end; ++j) val += hp[j].temp2[row + int64_t(li) * nout];
         const int jo = li < d.split ? li : li + d.gap;
+        double val = d.accum ? d.Y[row + int64_t(jo) * d.ldy] : y[tile][v];
+        for (int j = inf.hp_begin; j < inf.hp_end; ++j) val += hp[j].temp2[row + int64_t(li) * nout];
         d.Y[row + int64_t(jo) * d.ldy] = val;
       }
     }
@@ -637,7 +637,7 @@ __global__ void __launch_bounds__(256) k_fused_terms4(const int32_t* __restrict_
 #pragma unroll
   for (int q = 0; q < 4; ++q) y[q] = dbl4{0.0, 0.0, 0.0, 0.0};
   int buf = 0;
-  for (int a = tb; a >= 0; a = tv.b_parent[a]) {
+  for (int a = d.accum ? -1 : tb; a >= 0; a = tv.b_parent[a]) {
     for (int it = tv.group_ptr[a]; it < tv.group_ptr[a + 1]; ++it) {
       const TermT<TS> T = tree_terms<TS>(tv)[it];
       const TS* M;
@@ -755,9 +755,9 @@ __global__ void __launch_bounds__(256) k_fused_terms4(const int32_t* __restrict_
       const int r = 16 * tile + lk + 4 * v;
       if (tile < ntile && r < nout_w && li < w) {
         const int row = rout0 + r;
-        double val = y[tile][v];
-        for (int j = inf.hp_begin; j < inf.hp_end; ++j) val += hp[j].temp2[row + int64_t(li) * nout];
         const int jo = li < d.split ? li : li + d.gap;
+        double val = d.accum ? d.Y[row + int64_t(jo) * d.ldy] : y[tile][v];
+        for (int j = inf.hp_begin; j < inf.hp_end; ++j) val += hp[j].temp2[row + int64_t(li) * nout];
         d.Y[row + int64_t(jo) * d.ldy] = val;
       }
     }
@@ -789,6 +789,141 @@ void launch_fused_terms(const int32_t* tlist, size_t n, const TDesc* td, const T
 }  // namespace hm
 
 namespace hm {
+
+// Nearfield targets of at most 256 x 256: C[tau, sigma] = sum_i L_i core_i R_i^T +
+// sum_j A[tau, rho_j] B[rho_j, sigma] over the pairs of two dense leaves,
+// evaluated directly (S applied to the identity, the nearfield step of
+// Algorithm 4, without forming S I column block by column block). Pairs with a
+// subdivided factor are added afterwards through identity panels. One
+// workgroup per 64 x 64 sub-block (item = target, row block, column block);
+// wave q owns columns [16q, 16q + 16) of it, so every term panel is read once
+// per sub-block instead of once per 16 columns.
+__global__ void __launch_bounds__(256) k_near_direct(const int32_t* __restrict__ items,
+                                                    const int32_t* __restrict__ blocks,
+                                                    const int64_t* __restrict__ coff,
+                                                    const int32_t* __restrict__ pptr,
+                                                    const int32_t* __restrict__ pairs, TreeView tv, MatView ma,
+                                                    MatView mb, double* __restrict__ cpool) {
+  const int t = items[2 * blockIdx.x], rc = items[2 * blockIdx.x + 1];
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tb = blocks[t];
+  const int tau = tv.b_tau[tb], sig = tv.b_sigma[tb];
+  const int mt = tv.c_size[tau], nt = tv.c_size[sig];
+  const int rb0 = 64 * (rc >> 16), cb0 = 64 * (rc & 0xffff);  // sub-block origin
+  const int m = min(64, mt - rb0);                               // rows of this sub-block
+  const int n = nt;
+  const int col0 = cb0 + 16 * wid;
+  if (col0 >= min(n, cb0 + 64)) return;  // the whole wave leaves; no barriers follow
+  const int out0 = tv.c_begin[tau] + rb0, in0 = tv.c_begin[sig];
+  const int ntile = (m + 15) >> 4;
+  const int jc = col0 + li;  // column of this lane in B operands and in the output
+  const bool jok = jc < n && jc < cb0 + 64;
+  dbl4 y[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) y[q] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int a = tb; a >= 0; a = tv.b_parent[a]) {
+    for (int it = tv.group_ptr[a]; it < tv.group_ptr[a + 1]; ++it) {
+      const Term T = tv.terms[it];
+      const int kl = T.kl, kr = T.kr;
+      const int64_t rrow = int64_t(in0 + jc - T.rrow0);  // R row of this lane's column
+      // V = core R_slab^T (kl x 16) in accumulator layout: V[ob][v] = V(16 ob + lk + 4 v, li)
+      const int nob = (kl + 15) >> 4;
+      dbl4 V[4];
+      if (T.core) {
+        const int ks = (kr + 3) >> 2;
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+          V[ob] = dbl4{0.0, 0.0, 0.0, 0.0};
+          if (ob < nob) {
+            const int i = 16 * ob + li;
+#pragma unroll
+            for (int st = 0; st < 16; ++st) {
+              if (st < ks) {
+                const int cc = 4 * st + lk;
+                const double av = (i < kl && cc < kr) ? T.core[i + int64_t(cc) * kl] : 0.0;
+                double bv = 0.0;
+                if (cc < kr && jok) bv = T.rtrans ? T.R[cc + rrow * T.ldr] : T.R[rrow + int64_t(cc) * T.ldr];
+                V[ob] = mfma4(av, bv, V[ob]);
+              }
+            }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int cc = 16 * ob + lk + 4 * v;
+            double val = 0.0;
+            if (ob < nob && cc < kr && jok) val = T.rtrans ? T.R[cc + rrow * T.ldr] : T.R[rrow + int64_t(cc) * T.ldr];
+            V[ob][v] = val;
+          }
+        }
+      }
+      // y += L_tau V
+      const int64_t lr = int64_t(out0 - T.lrow0);
+#pragma unroll
+      for (int tile = 0; tile < 4; ++tile) {
+        if (tile < ntile) {
+          const int r = 16 * tile + li;
+#pragma unroll
+          for (int ob = 0; ob < 4; ++ob) {
+            if (ob < nob) {
+#pragma unroll
+              for (int s4 = 0; s4 < 4; ++s4) {
+                const int cc = 16 * ob + 4 * s4 + lk;
+                const double av = (cc < kl && r < m) ? T.L[(lr + r) + int64_t(cc) * T.ldl] : 0.0;
+                y[tile] = mfma4(av, V[ob][s4], y[tile]);
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  // dense pairs: y += A[tau, rho] B[rho, sigma][:, slab]
+  for (int p = pptr[t]; p < pptr[t + 1]; ++p) {
+    const int qa = pairs[2 * p], qb = pairs[2 * p + 1];
+    const int nr = tv.c_size[tv.b_sigma[qa]];
+    const double* Ab = ma.pool + ma.off[qa] + rb0;  // rows of this sub-block, leading dimension mt
+    const double* Bb = mb.pool + mb.off[qb];        // nr x n, column-major
+    const int ks = (nr + 3) >> 2;
+    for (int st = 0; st < ks; ++st) {
+      const int cc = 4 * st + lk;
+      const double bv = (cc < nr && jok) ? Bb[cc + int64_t(jc) * nr] : 0.0;
+#pragma unroll
+      for (int tile = 0; tile < 4; ++tile) {
+        if (tile < ntile) {
+          const int r = 16 * tile + li;
+          const double av = (cc < nr && r < m) ? Ab[r + int64_t(cc) * mt] : 0.0;
+          y[tile] = mfma4(av, bv, y[tile]);
+        }
+      }
+    }
+  }
+  double* Cb = cpool + coff[t] + rb0;  // C block is mt x n, column-major
+#pragma unroll
+  for (int tile = 0; tile < 4; ++tile) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * tile + lk + 4 * v;
+      if (tile < ntile && r < m && jok) Cb[r + int64_t(jc) * mt] = y[tile][v];
+    }
+  }
+}
+
+void launch_near_direct(const int32_t* items, int64_t nitems, const int32_t* blocks, const int64_t* coff,
+                        const int32_t* pptr, const int32_t* pairs, const TreeView& tv, const MatView& ma,
+                        const MatView& mb, double* cpool, hipStream_t s) {
+  const int64_t maxg = int64_t(1) << 30;
+  for (int64_t b = 0; b < nitems; b += maxg) {
+    const unsigned cnt = unsigned(std::min(maxg, nitems - b));
+    hipLaunchKernelGGL(k_near_direct, dim3(cnt), dim3(256), 0, s, items + 2 * b, blocks, coff, pptr, pairs, tv, ma,
+                       mb, cpool);
+    HM_CHECK_HIP(hipGetLastError());
+  }
+}
 
 __global__ void k_to_float(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;

@@ -73,7 +73,8 @@ struct TDesc {
   int32_t split, gap;  // output column j goes to j (j < split) or j + gap
   int32_t trans;
   int32_t xident;      // X is the identity restricted to columns [xcol0, xcol0 + w)
-  int32_t xcol0, pad;
+  int32_t xcol0;
+  int32_t accum;       // 1: Y += the pair results only (the terms were evaluated elsewhere)
 };
 
 struct TInfo {

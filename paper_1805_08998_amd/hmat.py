@@ -18,11 +18,11 @@ HMAT_ERR_DEVICE, HMAT_ERR_OOM, HMAT_ERR_INTERNAL = 4, 5, 6
 HMAT_FP64, HMAT_FP32_APPLY, HMAT_BF16_SKETCH = 0, 1, 2
 HMAT_RANK_ADAPTIVE, HMAT_RANK_PREDICT = 0, 1
 KERN_NAMES = ["term_reduce", "leaf_reduce", "subtree_expand", "gather", "compress", "fused_terms", "fused_terms4",
-              "k7"]
+              "near_direct"]
 # device kernel(s) of each timed family
 KERN_SYMBOLS = ["k_term_reduce", "k_leaf_reduce", "k_subtree_expand", "k_gather_mfma",
                 "k_orth_append+k_probe_residual+k_check+k_core+k_write_factors", "k_fused_terms",
-                "k_fused_terms4", ""]
+                "k_fused_terms4", "k_near_direct"]
 KERNELS = {"laplace_4pi": 0, "inv_dist": 1, "exp": 2}
 
 
@@ -49,7 +49,8 @@ class hmat_stats(C.Structure):
                 ("kern_launches", C.c_int64 * 8), ("kern_time", C.c_double * 8), ("kern_bytes", C.c_double * 8),
                 ("kern_flops", C.c_double * 8), ("t_host", C.c_double * 8), ("t_alloc", C.c_double),
                 ("n_malloc", C.c_int64), ("n_cache_release", C.c_int64), ("target_passes", C.c_int64),
-                ("streams_used", C.c_int32), ("pad_s", C.c_int32)]
+                ("streams_used", C.c_int32), ("pad_s", C.c_int32), ("n_near_direct", C.c_int64),
+                ("t_near_panels", C.c_double)]
 
     def as_dict(self):
         d = {}
