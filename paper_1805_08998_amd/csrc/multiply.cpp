@@ -117,8 +117,8 @@ struct Coef {
   double a = 0, b = 0, f = 0;
 };
 enum { K_TERM = 0, K_LEAF = 1, K_EXPAND = 2, K_GATHER = 3, K_COMPRESS = 4, K_FUSED = 5, K_FUSED4 = 6, K_NEAR = 7 };
-// targets whose clusters both have at most FUSED_MAX (one wave) or FUSED4_MAX (four
-// waves) rows use the fused MFMA kernels
+// nearfield targets whose clusters both have at most FUSED_MAX (one wave) or FUSED4_MAX
+// (four waves) rows use the fused MFMA kernels for their pairs
 constexpr int FUSED_MAX = 64;
 constexpr int FUSED4_MAX = 256;
 
@@ -726,8 +726,11 @@ void build_chunk(const Ctx& c, Chunk& ch, bool features) {
     const bool direct = ch.near && c.m_of(b) <= NEAR_MAX && c.n_of(b) <= NEAR_MAX;
     ch.direct[i] = direct;
     const double mt = t.c_size[t.b_tau[b]], nt_ = t.c_size[t.b_sigma[b]];
-    const bool small1 = mt <= FUSED_MAX && nt_ <= FUSED_MAX;
-    const bool small = mt <= FUSED4_MAX && nt_ <= FUSED4_MAX;
+    // the fused kernels serve nearfield targets that add pair results to the direct
+    // kernel's output; farfield targets of every size use term_reduce + gather, which
+    // measured faster on them than the fused kernels
+    const bool small1 = ch.near && mt <= FUSED_MAX && nt_ <= FUSED_MAX;
+    const bool small = small1 || (ch.near && mt <= FUSED4_MAX && nt_ <= FUSED4_MAX);
     ch.is_small[i] = small1 ? 1 : small ? 2 : 0;
     if (small1) ch.small.push_back(i);
     else if (small) ch.small4.push_back(i);
