@@ -263,6 +263,46 @@ def run_batched(H, args):
         H.hmat_tree_destroy(tr)
 
 
+def copy_probe():
+    """A plain device copy of known size (1 GiB read, 1 GiB written per launch,
+    five launches), the calibration run for the HBM traffic counters."""
+    import torch
+    nbytes = 1 << 30
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "launches": 5}))
+
+
+def product_source_hash():
+    """Hash of the apply-kernel sources: traffic figures measured on other sources are stale."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("product.hip", "product_kernels.h"):
+        with open(os.path.join(ROOT, "paper_1805_08998_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed rocprofv3
+    counter summary (a line 'traffic <kernel> <workload> <bytes> <source hash>'),
+    or None when there is none or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    want = product_source_hash()
+    with open(path) as fh:
+        for line in fh:
+            f = line.strip().strip("`").split()
+            if len(f) == 5 and f[0] == "traffic" and f[1] == kernel and f[2] == workload and f[4] == want:
+                return float(f[3])
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -279,7 +319,12 @@ def main():
                     help="timed plain products after the learned ones (learned mode only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run the copy kernel that calibrates the traffic counters")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the product runs on a "
               "single MI355X (sharding over GPUs is described in DESIGN.md, not built)", file=sys.stderr)
@@ -387,7 +432,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-        "traffic": None,
+        "traffic": measured_traffic(H.KERN_SYMBOLS[dom], w.name),
         "avg_launch_us": 1e6 * avg,
         "instrumented_step_s": kdt,
         "launches": int(kl[dom]),
