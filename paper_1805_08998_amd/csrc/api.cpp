@@ -47,6 +47,21 @@ static size_t g_cached_bytes = 0;
 
 void set_current_stream(hipStream_t s) { g_stream = s; }
 
+void forget_stream(hipStream_t s) {
+  // called after s has been synchronized and before it is destroyed: the blocks freed
+  // on it are idle, and their events must not be queried once the stream is gone
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  for (auto& kv : g_cache)
+    for (auto& cb : kv.second)
+      if (cb.ev && cb.stream == s) {
+        (void)hipEventSynchronize(cb.ev);
+        (void)hipEventDestroy(cb.ev);
+        cb.ev = nullptr;
+        cb.stream = nullptr;
+      }
+  (void)hipGetLastError();
+}
+
 size_t dev_free_bytes() {
   size_t fb = 0, tb = 0;
   HM_CHECK_HIP(hipMemGetInfo(&fb, &tb));
@@ -95,8 +110,10 @@ static std::vector<CachedBlock> take_blocks_locked(size_t need) {
 static void free_blocks(std::vector<CachedBlock>& v) {
   const double t0 = now_seconds();
   for (auto& cb : v) {
-    (void)hipEventSynchronize(cb.ev);
-    (void)hipEventDestroy(cb.ev);
+    if (cb.ev) {
+      (void)hipEventSynchronize(cb.ev);
+      (void)hipEventDestroy(cb.ev);
+    }
     (void)hipFree(cb.p);
   }
   v.clear();
@@ -133,16 +150,23 @@ void* dev_alloc(size_t bytes) {
     for (auto it = g_cache.lower_bound({dev, rs});
          it != g_cache.end() && it->first.first == dev && it->first.second <= rs + rs / 2; ++it) {
       auto& v = it->second;
-      for (size_t i = 0; i < v.size(); ++i)
-        if (v[i].stream == g_stream || hipEventQuery(v[i].ev) == hipSuccess) {
+      for (size_t i = 0; i < v.size(); ++i) {
+        bool ok = !v[i].ev || v[i].stream == g_stream;
+        if (!ok) {
+          const hipError_t q = hipEventQuery(v[i].ev);
+          ok = q == hipSuccess;
+          if (q != hipSuccess) (void)hipGetLastError();  // not ready (or unusable): leave it
+        }
+        if (ok) {
           p = v[i].p;
           const size_t got = it->first.second;
-          (void)hipEventDestroy(v[i].ev);
+          if (v[i].ev) (void)hipEventDestroy(v[i].ev);
           v.erase(v.begin() + i);
           g_cached_bytes -= got;
           g_live[p] = {dev, got};
           return p;
         }
+      }
     }
   }
   const double t0 = now_seconds();

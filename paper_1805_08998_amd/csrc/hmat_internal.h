@@ -41,6 +41,9 @@ void* dev_alloc(size_t bytes);
 void dev_free(void* p);
 // stream on which freed blocks may still be in use (set by every entry point that launches work)
 void set_current_stream(hipStream_t s);
+// Before destroying a stream the library created: marks the cached blocks freed on it
+// as idle (the stream must have been synchronized).
+void forget_stream(hipStream_t s);
 struct AllocCounters {
   double seconds = 0;  // in hipMalloc / hipFree
   int64_t mallocs = 0, releases = 0;

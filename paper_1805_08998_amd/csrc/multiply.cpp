@@ -98,8 +98,48 @@ DfsInfo dfs_order(const Tree& t) {
 struct DevMat {
   DevBuf<int64_t> kpref;
   std::vector<int64_t> hkpref;
-  MatView view(const HMat* M) const { return MatView{M->pool.p, M->d_rank.p, M->d_off.p, kpref.p, M->pool32.p}; }
+  DevBuf<LeafRec> row_rec, col_rec;
+  DevBuf<DfsRec> dfs_rec;
+  MatView view(const HMat* M) const {
+    return MatView{M->pool.p, M->d_rank.p, M->d_off.p, kpref.p, M->pool32.p, row_rec.p, col_rec.p, dfs_rec.p};
+  }
 };
+
+// Packed leaf records of M for the subtree kernels (block-row and block-column lists,
+// depth-first order).
+void build_leaf_recs(const HMat* M, const DfsInfo& d, DevMat& dm, hipStream_t s) {
+  const Tree& t = *M->tree;
+  auto rec = [&](int32_t b, bool row) {
+    LeafRec r{};
+    const int32_t oth = row ? t.b_sigma[b] : t.b_tau[b];
+    r.off = M->off[b];
+    r.o0 = t.c_begin[oth];
+    r.on = t.c_size[oth];
+    r.k = t.b_kind[b] == KIND_F ? M->rank[b] : -1;
+    r.m = t.c_size[t.b_tau[b]];
+    r.n = t.c_size[t.b_sigma[b]];
+    r.dfs = d.dfs_of_block[b];
+    return r;
+  };
+  std::vector<LeafRec> rr(t.brow_blk.size()), cr(t.bcol_blk.size());
+  for (size_t p = 0; p < rr.size(); ++p) rr[p] = rec(t.brow_blk[p], true);
+  for (size_t p = 0; p < cr.size(); ++p) cr[p] = rec(t.bcol_blk[p], false);
+  std::vector<DfsRec> dr(d.dfs_block.size());
+  for (size_t i = 0; i < dr.size(); ++i) {
+    const int32_t b = d.dfs_block[i];
+    DfsRec& x = dr[i];
+    x.off = M->off[b];
+    x.r0 = t.c_begin[t.b_tau[b]];
+    x.c0 = t.c_begin[t.b_sigma[b]];
+    x.m = t.c_size[t.b_tau[b]];
+    x.n = t.c_size[t.b_sigma[b]];
+    x.k = t.b_kind[b] == KIND_F ? M->rank[b] : -1;
+    x.pad = 0;
+  }
+  dm.row_rec.upload(rr, s);
+  dm.col_rec.upload(cr, s);
+  dm.dfs_rec.upload(dr, s);
+}
 
 void build_kpref(const HMat* M, const DfsInfo& d, DevMat& dm, hipStream_t s) {
   dm.hkpref.assign(d.dfs_block.size() + 1, 0);
@@ -251,66 +291,121 @@ void symbolic(Ctx& c) {
   // Pair entries are triples (rho, block tau x rho, block rho x sigma); the blocks of
   // a son pair follow from the parents' ids because sons of a block are stored
   // tau-son-major and contiguously: son (i, j) of block x is child0[x] + i * #sons(sigma_x) + j.
+  // The blocks of a level are split into contiguous ranges handled by worker threads;
+  // their outputs are concatenated in block order, so the result does not depend on
+  // the number of threads.
   std::vector<int32_t> cur_ptr{0, 1}, cur_rho{0, 0, 0};  // level 0: the root, rho = I
   int64_t lev_first = 0;                                  // first block id of the current level
-  auto leaf_pairs = [&](int64_t b, const int32_t* r, int cnt) {
-    for (int i = 0; i < 3 * cnt; ++i) c.hrho.push_back(r[i]);
-    c.hptr[b + 1] = int32_t(c.hrho.size() / 3);
+  if (t.b_kind[0] != KIND_INNER) {
+    c.hrho.insert(c.hrho.end(), cur_rho.begin(), cur_rho.end());
+    c.hptr[1] = 1;
+  }
+  struct Part {
+    std::vector<SymTerm> sym;
+    std::vector<int32_t> nxt_rho, leaf_rho;
+    std::vector<int32_t> n_terms, n_nxt, n_leaf;  // per son, in son order
+    int64_t first_child = -1;
+    std::string err;
   };
-  if (t.b_kind[0] != KIND_INNER) leaf_pairs(0, cur_rho.data(), 1);
-  else c.hptr[1] = 0;
-  c.group_ptr_h[1] = 0;
+  const unsigned hw = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
   for (int lev = 0; lev < t.depth; ++lev) {
     const int64_t lb = t.level_begin[lev], le = t.level_begin[lev + 1];
-    std::vector<int32_t> nxt_ptr{0}, nxt_rho;
-    int64_t next_expected = t.level_begin[lev + 1];
-    for (int64_t b = lb; b < le; ++b) {
-      if (t.b_kind[b] != KIND_INNER) continue;
-      const int32_t* rb = cur_rho.data() + 3 * cur_ptr[b - lev_first];
-      const int nr = cur_ptr[b - lev_first + 1] - cur_ptr[b - lev_first];
-      const int ns = t.c_nchild[t.b_sigma[b]];
-      for (int ci = 0; ci < t.b_nchild[b]; ++ci) {
-        const int32_t ch = t.b_child0[b] + ci;
-        if (ch != next_expected) throw Error(HMAT_ERR_INTERNAL, "block order");
-        ++next_expected;
-        const int it = ci / ns, is = ci % ns;  // son indices in tau_b and sigma_b
-        const size_t h0 = nxt_rho.size();
-        for (int q = 0; q < nr; ++q) {
-          const int32_t rho = rb[3 * q], qa = rb[3 * q + 1], qb = rb[3 * q + 2];
-          if (t.c_nchild[rho] == 0) {
-            // middle cluster is a leaf: both factors are nearfield leaves of the parent level
-            c.sym.push_back(SymTerm{T_GAP, ch, qa, qb, t.c_size[rho], t.c_size[rho], 0, -1});
-            continue;
-          }
-          const int nrho = t.c_nchild[rho];
-          for (int i = 0; i < nrho; ++i) {
-            const int32_t r2 = t.c_child0[rho] + i;
-            const int32_t b1 = t.b_child0[qa] + it * nrho + i;  // tau' x rho'
-            const int32_t b2 = t.b_child0[qb] + i * ns + is;    // rho' x sigma'
-            const bool f1 = t.b_kind[b1] == KIND_F, f2 = t.b_kind[b2] == KIND_F;
-            if (f1 && f2) {
-              if (c.rank_a(b1) && c.rank_b(b2))
-                c.sym.push_back(SymTerm{T_FF, ch, b1, b2, c.rank_a(b1), c.rank_b(b2), 0, -1});
-            } else if (f1) {
-              if (c.rank_a(b1)) c.sym.push_back(SymTerm{T_FH, ch, b1, b2, c.rank_a(b1), c.rank_a(b1), 0, -1});
-            } else if (f2) {
-              if (c.rank_b(b2)) c.sym.push_back(SymTerm{T_HF, ch, b1, b2, c.rank_b(b2), c.rank_b(b2), 0, -1});
-            } else {
-              nxt_rho.push_back(r2);
-              nxt_rho.push_back(b1);
-              nxt_rho.push_back(b2);
+    const int64_t nlev = le - lb;
+    const int nparts = nlev >= 4096 ? int(hw) : 1;
+    std::vector<Part> parts(nparts);
+    auto work = [&](int pi) {
+      Part& P = parts[pi];
+      const int64_t b0 = lb + nlev * pi / nparts, b1 = lb + nlev * (pi + 1) / nparts;
+      for (int64_t b = b0; b < b1; ++b) {
+        if (t.b_kind[b] != KIND_INNER) continue;
+        const int32_t* rb = cur_rho.data() + 3 * cur_ptr[b - lev_first];
+        const int nr = cur_ptr[b - lev_first + 1] - cur_ptr[b - lev_first];
+        const int ns = t.c_nchild[t.b_sigma[b]];
+        for (int ci = 0; ci < t.b_nchild[b]; ++ci) {
+          const int32_t ch = t.b_child0[b] + ci;
+          if (P.first_child < 0) P.first_child = ch;
+          const int it = ci / ns, is = ci % ns;  // son indices in tau_b and sigma_b
+          const size_t s0 = P.sym.size(), h0 = P.nxt_rho.size();
+          for (int q = 0; q < nr; ++q) {
+            const int32_t rho = rb[3 * q], qa = rb[3 * q + 1], qb = rb[3 * q + 2];
+            if (t.c_nchild[rho] == 0) {
+              // middle cluster is a leaf: both factors are nearfield leaves of the parent level
+              P.sym.push_back(SymTerm{T_GAP, ch, qa, qb, t.c_size[rho], t.c_size[rho], 0, -1});
+              continue;
+            }
+            const int nrho = t.c_nchild[rho];
+            for (int i = 0; i < nrho; ++i) {
+              const int32_t r2 = t.c_child0[rho] + i;
+              const int32_t b1x = t.b_child0[qa] + it * nrho + i;  // tau' x rho'
+              const int32_t b2x = t.b_child0[qb] + i * ns + is;    // rho' x sigma'
+              const bool f1 = t.b_kind[b1x] == KIND_F, f2 = t.b_kind[b2x] == KIND_F;
+              if (f1 && f2) {
+                if (c.rank_a(b1x) && c.rank_b(b2x))
+                  P.sym.push_back(SymTerm{T_FF, ch, b1x, b2x, c.rank_a(b1x), c.rank_b(b2x), 0, -1});
+              } else if (f1) {
+                if (c.rank_a(b1x)) P.sym.push_back(SymTerm{T_FH, ch, b1x, b2x, c.rank_a(b1x), c.rank_a(b1x), 0, -1});
+              } else if (f2) {
+                if (c.rank_b(b2x)) P.sym.push_back(SymTerm{T_HF, ch, b1x, b2x, c.rank_b(b2x), c.rank_b(b2x), 0, -1});
+              } else {
+                P.nxt_rho.push_back(r2);
+                P.nxt_rho.push_back(b1x);
+                P.nxt_rho.push_back(b2x);
+              }
             }
           }
+          P.n_terms.push_back(int32_t(P.sym.size() - s0));
+          const int cnt = int((P.nxt_rho.size() - h0) / 3);
+          if (t.b_kind[ch] != KIND_INNER) {  // a leaf keeps its pairs; they leave the next level's list
+            P.leaf_rho.insert(P.leaf_rho.end(), P.nxt_rho.begin() + h0, P.nxt_rho.end());
+            P.nxt_rho.resize(h0);
+            P.n_leaf.push_back(cnt);
+            P.n_nxt.push_back(0);
+          } else {
+            P.n_leaf.push_back(0);
+            P.n_nxt.push_back(cnt);
+          }
         }
-        c.group_ptr_h[ch + 1] = int32_t(c.sym.size());
-        const int cnt = int((nxt_rho.size() - h0) / 3);
-        if (t.b_kind[ch] != KIND_INNER) {
-          leaf_pairs(ch, nxt_rho.data() + h0, cnt);
-          nxt_rho.resize(h0);
-        } else {
-          c.hptr[ch + 1] = int32_t(c.hrho.size() / 3);
+      }
+    };
+    if (nparts == 1) {
+      work(0);
+    } else {
+      std::vector<std::thread> th;
+      for (int pi = 0; pi < nparts; ++pi) th.emplace_back([&, pi]() {
+        try {
+          work(pi);
+        } catch (const std::exception& e) {
+          parts[pi].err = e.what();
         }
-        nxt_ptr.push_back(int32_t(nxt_rho.size() / 3));
+      });
+      for (auto& x : th) x.join();
+      for (auto& P : parts)
+        if (!P.err.empty()) throw Error(HMAT_ERR_INTERNAL, P.err);
+    }
+    // concatenate in block order and fill the CSR pointers of the sons (= the next level)
+    std::vector<int32_t> nxt_ptr{0}, nxt_rho;
+    int64_t next_expected = t.level_begin[lev + 1];
+    size_t sym_total = c.sym.size(), nxt_total = 0;
+    for (auto& P : parts) sym_total += P.sym.size(), nxt_total += P.nxt_rho.size();
+    c.sym.reserve(sym_total);
+    nxt_rho.reserve(nxt_total);
+    for (auto& P : parts) {
+      if (P.n_terms.empty()) continue;
+      if (P.first_child != next_expected) throw Error(HMAT_ERR_INTERNAL, "block order");
+      size_t lp = 0;
+      next_expected += int64_t(P.n_terms.size());
+      const int64_t ch0 = P.first_child;
+      int64_t spos = int64_t(c.sym.size());
+      c.sym.insert(c.sym.end(), P.sym.begin(), P.sym.end());
+      nxt_rho.insert(nxt_rho.end(), P.nxt_rho.begin(), P.nxt_rho.end());
+      for (size_t k = 0; k < P.n_terms.size(); ++k) {
+        const int64_t ch = ch0 + int64_t(k);
+        spos += P.n_terms[k];
+        c.group_ptr_h[ch + 1] = int32_t(spos);
+        if (P.n_leaf[k]) c.hrho.insert(c.hrho.end(), P.leaf_rho.begin() + 3 * lp, P.leaf_rho.begin() + 3 * (lp + P.n_leaf[k]));
+        lp += P.n_leaf[k];
+        c.hptr[ch + 1] = int32_t(c.hrho.size() / 3);
+        nxt_ptr.push_back(nxt_ptr.back() + P.n_nxt[k]);
       }
     }
     if (int64_t(nxt_ptr.size()) != t.level_begin[lev + 2] - t.level_begin[lev + 1] + 1)
@@ -1263,6 +1358,8 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   c.dfs = dfs_order(*t);
   build_kpref(A, c.dfs, c.da, s);
   build_kpref(B, c.dfs, c.db, s);
+  build_leaf_recs(A, c.dfs, c.da, s);
+  build_leaf_recs(B, c.dfs, c.db, s);
   c.lowp = opts.o.precision == HMAT_FP32_APPLY;
   if (c.lowp) {
     for (HMat* M : {A, B}) {
@@ -1663,6 +1760,7 @@ hmat_status multiply_batched(HMat* const* A, HMat* const* B, int32_t count, doub
         }
         if (s) {
           (void)hipStreamSynchronize(s);
+          forget_stream(s);
           (void)hipStreamDestroy(s);
         }
       });

@@ -226,36 +226,34 @@ __global__ void __launch_bounds__(64) k_leaf_reduce(const int64_t* __restrict__ 
   const int64_t g = g0 + blockIdx.x;
   const int k = find_owner(pre, ntask, g);
   const Task tk = tasks[k];
-  const int b = dfs_block[tk.lo + int(g - pre[k])];
-  if (tv.b_kind[b] != KIND_F) return;
+  const int dfs = tk.lo + int(g - pre[k]);
   const MatView& mv = tk.mat ? mb : ma;
-  const int kr = mv.rank[b];
-  if (kr == 0) return;
+  const DfsRec L = mv.dfs_rec[dfs];
+  const int kr = L.k;
+  if (kr <= 0) return;  // nearfield leaf (-1) or rank 0
   const double* X;
   int ldx, w, xident, xc0;
   task_input(tk, td, X, ldx, w, xident, xc0);
   if (w == 0) return;
   const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
-  const int qt = tv.b_tau[tk.q], qs = tv.b_sigma[tk.q];
-  const int bt = tv.b_tau[b], bs = tv.b_sigma[b];
-  const int m = tv.c_size[bt], n = tv.c_size[bs];
-  const TS* base = mat_pool<TS>(mv) + mv.off[b];
+  const int m = L.m, n = L.n;
+  const TS* base = mat_pool<TS>(mv) + L.off;
   const TS* M;
   int rows, ro, ldm;
   if (!tk.trans) {
     M = base + int64_t(kr) * m;
     ldm = n;
     rows = n;
-    ro = tv.c_begin[bs] - tv.c_begin[qs];
+    ro = L.c0 - tv.c_begin[tv.b_sigma[tk.q]];
   } else {
     M = base;
     ldm = m;
     rows = m;
-    ro = tv.c_begin[bt] - tv.c_begin[qt];
+    ro = L.r0 - tv.c_begin[tv.b_tau[tk.q]];
   }
   const int nkb = (kr + 15) >> 4;
   const int ks = (rows + 3) >> 2;
-  double* T = ws + tk.tws + (mv.kpref[tv.b_dfs[b]] - mv.kpref[tk.lo]) * PW;
+  double* T = ws + tk.tws + (mv.kpref[dfs] - mv.kpref[tk.lo]) * PW;
   for (int kb = 0; kb < nkb; ++kb) {
     dbl4 U = dbl4{0.0, 0.0, 0.0, 0.0};
     const int c = 16 * kb + li;
@@ -301,33 +299,32 @@ __global__ void __launch_bounds__(64) k_subtree_expand(const int64_t* __restrict
   dbl4 y[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) y[q] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const LeafRec* lst = tk.trans ? mv.col_rec : mv.row_rec;
+  const int* lptr = tk.trans ? tv.bcol_ptr : tv.brow_ptr;
   for (int a = c; a >= 0; a = tv.c_parent[a]) {
-    const int* lst = tk.trans ? tv.bcol_blk : tv.brow_blk;
-    int p0 = tk.trans ? tv.bcol_ptr[a] : tv.brow_ptr[a];
-    const int p1 = tk.trans ? tv.bcol_ptr[a + 1] : tv.brow_ptr[a + 1];
+    int p0 = lptr[a];
+    const int p1 = lptr[a + 1];
     {  // the list is sorted by the first position of the other cluster: skip to in0
       int lo = p0, hi = p1;
       while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        const int bm = lst[mid];
-        if (tv.c_begin[tk.trans ? tv.b_tau[bm] : tv.b_sigma[bm]] < in0) lo = mid + 1;
+        if (lst[mid].o0 < in0) lo = mid + 1;
         else hi = mid;
       }
       p0 = lo;
     }
+    const int roff = row_lo - tv.c_begin[a];  // first output row inside the leaves' rows
     for (int p = p0; p < p1; ++p) {
-      const int b = lst[p];
-      const int oth = tk.trans ? tv.b_tau[b] : tv.b_sigma[b];
-      const int o0 = tv.c_begin[oth], o1 = o0 + tv.c_size[oth];
+      const LeafRec L = lst[p];
+      const int o0 = L.o0, o1 = o0 + L.on;
       if (o0 >= in1) break;
       if (o1 > in1) continue;
-      const int m = tv.c_size[tv.b_tau[b]], n = tv.c_size[tv.b_sigma[b]];
-      const TS* base = mat_pool<TS>(mv) + mv.off[b];
-      const int roff = row_lo - tv.c_begin[a];  // first output row inside the leaf's rows
-      if (tv.b_kind[b] == KIND_F) {
-        const int k = mv.rank[b];
+      const int m = L.m, n = L.n;
+      const TS* base = mat_pool<TS>(mv) + L.off;
+      if (L.k >= 0) {
+        const int k = L.k;
         if (k == 0) continue;
-        const double* Tm = ws + tk.tws + (mv.kpref[tv.b_dfs[b]] - mv.kpref[tk.lo]) * PW;
+        const double* Tm = ws + tk.tws + (mv.kpref[L.dfs] - mv.kpref[tk.lo]) * PW;
         const TS* P = tk.trans ? base + int64_t(k) * m : base;
         const int ldp = tk.trans ? n : m;
         const int ks = (k + 3) >> 2;

@@ -25,12 +25,33 @@ struct TermT {
 using Term = TermT<double>;
 using Term32 = TermT<float>;
 
+// A leaf block of one matrix as seen from a block row (or column) list: one 32-byte
+// record instead of a chain of dependent index loads.
+struct LeafRec {
+  int64_t off;     // element offset of the leaf's data in the pool
+  int32_t o0, on;  // position and size of the other cluster (sigma in a row list, tau in a column list)
+  int32_t k;       // farfield rank, -1 for a nearfield (dense) leaf
+  int32_t m, n;    // rows and columns of the leaf
+  int32_t dfs;     // depth-first leaf index
+};
+// The same, indexed by depth-first leaf index.
+struct DfsRec {
+  int64_t off;
+  int32_t r0, c0;  // first row and column position
+  int32_t m, n;
+  int32_t k;       // farfield rank, -1 for nearfield
+  int32_t pad;
+};
+
 struct MatView {
   const double* pool;
   const int32_t* rank;   // per block
   const int64_t* off;    // per block, element offset of the leaf data in pool
   const int64_t* kpref;  // per depth-first leaf index: prefix sum of farfield ranks
   const float* pool32;   // float copy of pool (mixed precision), else null
+  const LeafRec* row_rec;  // aligned with the tree's block-row lists (brow_blk)
+  const LeafRec* col_rec;  // aligned with the block-column lists (bcol_blk)
+  const DfsRec* dfs_rec;   // per depth-first leaf index
 };
 
 struct TreeView {

@@ -103,3 +103,51 @@ def test_product_sphere8k(H):
     pts = jitter(fibonacci_sphere(8192), 1e-3, 0)
     nbad, wf, wn, code = run_case(H, pts, 64, 0, ("laplace_4pi", 1.0, 0.0), ("exp", 1.0, 1.0), 1e-6)
     assert code == 0 and nbad == 0
+
+
+def test_product_duplicate_points(H):
+    """Every point twice: zero-extent clusters (Def. 2.2 allows no split there)."""
+    print("[product] 700 points, each twice, exp x exp", flush=True)
+    import numpy as np
+    p = fibonacci_sphere(700)
+    pts = np.ascontiguousarray(np.concatenate([p, p]))
+    nbad, wf, wn, code = run_case(H, pts, 32, 0, ("exp", 1.0, 0.0), ("exp", 1.0, 1.0), 1e-6)
+    assert code == 0 and nbad == 0
+
+
+def test_product_with_identity_and_zero(H):
+    """A I = A and A 0 = 0 with I and 0 given as H-matrices on the same tree
+    (rank-0 farfield leaves, dense identity or zero nearfield leaves)."""
+    import numpy as np
+    from oracle.hmatrix import HMatrix, Leaf, KIND_N
+    from tests.helpers import oracle_to_blocks
+    print("[product] sphere 2048: A I and A 0", flush=True)
+    pts = fibonacci_sphere(2048)
+    t = H.hmat_build_tree(pts, 32, 0.8, 0)
+    A, _ = H.hmat_assemble(t, "laplace_4pi", 1.0, 0.0, eps_in=1e-8)
+    Ao = exported_to_oracle(H, t, A)
+    for which in ("identity", "zero"):
+        Io = HMatrix(n=Ao.n, perm=Ao.perm)
+        for lf in Ao.leaves:
+            if lf.kind == KIND_F:
+                Io.leaves.append(Leaf(lf.r0, lf.m, lf.c0, lf.n, KIND_F, L=np.zeros((lf.m, 0)), R=np.zeros((lf.n, 0))))
+            else:
+                D = np.eye(lf.m) if (which == "identity" and lf.r0 == lf.c0 and lf.m == lf.n) else np.zeros((lf.m, lf.n))
+                Io.leaves.append(Leaf(lf.r0, lf.m, lf.c0, lf.n, KIND_N, D=D))
+        I = H.hmat_from_blocks(t, *oracle_to_blocks(Io))
+        C, code = H.hmat_multiply(A, I, 1e-6)
+        P = brute_force_product(Ao, exported_to_oracle(H, t, I))
+        Co = exported_to_oracle(H, t, C)
+        bad = 0
+        for lf in Co.leaves:
+            D = P[lf.r0:lf.r0 + lf.m, lf.c0:lf.c0 + lf.n]
+            r = check_block(D, KIND_F, 1e-6, U=lf.L, V=lf.R) if lf.kind == KIND_F else check_block(D, 2, 1e-6, Dc=lf.D)
+            bad += not r.ok
+            if which == "zero":
+                assert (lf.kind == KIND_F and lf.L.shape[1] == 0) or (lf.kind != KIND_F and not lf.D.any())
+        print(f"A {which}: {bad} blocks outside the bound", flush=True)
+        assert code == 0 and bad == 0
+        H.hmat_destroy(C)
+        H.hmat_destroy(I)
+    H.hmat_destroy(A)
+    H.hmat_tree_destroy(t)
