@@ -189,6 +189,9 @@ typedef struct {
    * other nearfield targets (identity panels) */
   int64_t n_near_direct;
   double t_near_panels;
+  /* size of the symbolic plan: low-rank terms created, pairs kept at leaves */
+  int64_t n_terms;
+  int64_t n_leaf_pairs;
 } hmat_stats;
 
 /* Kernel families of hmat_stats.kern_* */

@@ -271,6 +271,7 @@ struct Ctx {
     throw Error(HMAT_ERR_INTERNAL, "term panel outside the registered pools");
   }
 
+  ~Ctx();
   int32_t m_of(int32_t b) const { return t->c_size[t->b_tau[b]]; }
   int32_t n_of(int32_t b) const { return t->c_size[t->b_sigma[b]]; }
   int32_t rank_a(int32_t b) const { return A->rank[b]; }
@@ -278,11 +279,46 @@ struct Ctx {
 };
 
 // ------------------------------------------------------------------ symbolic restriction
+// Capacity of the large plan arrays is kept per host thread between products: they
+// reach hundreds of megabytes, and fresh allocations would be page-faulted in again
+// by every product. Only the capacity is reused; every product rebuilds the contents.
+struct PlanArena {
+  std::vector<SymTerm> sym;
+  std::vector<int32_t> hrho;
+  std::vector<Term> hterms;
+  std::vector<std::vector<SymTerm>> part_sym;
+  std::vector<std::vector<int32_t>> part_nxt, part_leaf;
+};
+PlanArena& plan_arena() {
+  static thread_local PlanArena a;
+  return a;
+}
+constexpr size_t kArenaKeepBytes = size_t(4) << 30;  // larger arrays are released after use
+
+Ctx::~Ctx() {
+  PlanArena& a = plan_arena();
+  if (sym.capacity() * sizeof(SymTerm) <= kArenaKeepBytes) {
+    sym.clear();
+    a.sym.swap(sym);
+  }
+  if (hrho.capacity() * sizeof(int32_t) <= kArenaKeepBytes) {
+    hrho.clear();
+    a.hrho.swap(hrho);
+  }
+  if (hterms.capacity() * sizeof(Term) <= kArenaKeepBytes) {
+    hterms.clear();
+    a.hterms.swap(hterms);
+  }
+}
+
 void symbolic(Ctx& c) {
   const Tree& t = *c.t;
   const int64_t nb = int64_t(t.b_tau.size());
   c.group_ptr_h.assign(nb + 1, 0);
   c.hptr.assign(nb + 1, 0);
+  PlanArena& arena = plan_arena();
+  c.sym.swap(arena.sym);
+  c.hrho.swap(arena.hrho);
   c.sym.clear();
   c.hrho.clear();
   // Breadth-first: the sons of the blocks of one level are generated in block-id
@@ -313,6 +349,19 @@ void symbolic(Ctx& c) {
     const int64_t nlev = le - lb;
     const int nparts = nlev >= 4096 ? int(hw) : 1;
     std::vector<Part> parts(nparts);
+    if (arena.part_sym.size() < size_t(nparts)) {
+      arena.part_sym.resize(nparts);
+      arena.part_nxt.resize(nparts);
+      arena.part_leaf.resize(nparts);
+    }
+    for (int pi = 0; pi < nparts; ++pi) {  // reuse capacity
+      parts[pi].sym.swap(arena.part_sym[pi]);
+      parts[pi].nxt_rho.swap(arena.part_nxt[pi]);
+      parts[pi].leaf_rho.swap(arena.part_leaf[pi]);
+      parts[pi].sym.clear();
+      parts[pi].nxt_rho.clear();
+      parts[pi].leaf_rho.clear();
+    }
     auto work = [&](int pi) {
       Part& P = parts[pi];
       const int64_t b0 = lb + nlev * pi / nparts, b1 = lb + nlev * (pi + 1) / nparts;
@@ -408,6 +457,11 @@ void symbolic(Ctx& c) {
         nxt_ptr.push_back(nxt_ptr.back() + P.n_nxt[k]);
       }
     }
+    for (int pi = 0; pi < nparts; ++pi) {
+      arena.part_sym[pi].swap(parts[pi].sym);
+      arena.part_nxt[pi].swap(parts[pi].nxt_rho);
+      arena.part_leaf[pi].swap(parts[pi].leaf_rho);
+    }
     if (int64_t(nxt_ptr.size()) != t.level_begin[lev + 2] - t.level_begin[lev + 1] + 1)
       throw Error(HMAT_ERR_INTERNAL, "level size");
     cur_ptr.swap(nxt_ptr);
@@ -434,6 +488,26 @@ struct TaskList {
     rpre.push_back(rpre.back() + (expand ? (t.c_lc_end[outc] - t.c_lc_begin[outc]) : 0));
   }
   int ntask() const { return int(tasks.size()); }
+  // host arrays handed between calls so that their capacity survives (the device
+  // arrays do not)
+  struct Host {
+    std::vector<Task> tasks;
+    std::vector<int64_t> lpre, rpre;
+  };
+  void take(Host& h) {
+    tasks.swap(h.tasks);
+    lpre.swap(h.lpre);
+    rpre.swap(h.rpre);
+    tasks.clear();
+    lpre.assign(1, 0);
+    rpre.assign(1, 0);
+    ws_len = 0;
+  }
+  void give(Host& h) {
+    tasks.swap(h.tasks);
+    lpre.swap(h.lpre);
+    rpre.swap(h.rpre);
+  }
   void upload(hipStream_t s) {
     d_tasks.upload(tasks, s);
     d_lpre.upload(lpre, s);
@@ -542,7 +616,11 @@ void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& poo
   double* P = pool_out.p;
   const double th0 = now_seconds();
   // FF cores: leaf reductions R_A^T L_B written straight into the pool
+  // the host lists keep their capacity between calls of this thread (page faults otherwise)
+  static thread_local TaskList::Host ff_keep, fh_keep;
   TaskList ff, fh;
+  ff.take(ff_keep);
+  fh.take(fh_keep);
   for (int32_t i : which) {
     const SymTerm& st = c.sym[i];
     if (st.type == T_FF) {
@@ -620,6 +698,8 @@ void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& poo
   }
   HM_CHECK_HIP(hipStreamSynchronize(s));
   c.st.t_host[6] += now_seconds() - tu;
+  ff.give(ff_keep);
+  fh.give(fh_keep);
   // device descriptors of these terms
   for (int32_t i : which) {
     const SymTerm& st = c.sym[i];
@@ -684,7 +764,9 @@ void publish_terms(Ctx& c, const std::vector<int32_t>& which) {
   } acc{c, t0};
   if (c.terms.n < c.hterms.size()) c.terms.alloc(c.hterms.size());
   if (which.empty()) return;
-  std::vector<Term> packed(which.size());
+  static thread_local std::vector<Term> packed_keep;
+  std::vector<Term>& packed = packed_keep;
+  packed.resize(which.size());
   for (size_t i = 0; i < which.size(); ++i) packed[i] = c.hterms[which[i]];
   DevBuf<int32_t> ids;
   ids.upload(which, c.s);
@@ -750,6 +832,33 @@ struct Chunk {
   bool near = false;
   std::vector<uint8_t> direct;
   std::vector<int32_t> dpptr, dpairs;  // per direct target (chunk order): dense pairs (A block, B block)
+  // empties the chunk for reuse, keeping host capacity and device buffers
+  void reset() {
+    blocks.clear();
+    info.clear();
+    pairs.clear();
+    for (TaskList* L : {&t1f, &t2f, &t1t, &t2t}) {
+      L->tasks.clear();
+      L->lpre.assign(1, 0);
+      L->rpre.assign(1, 0);
+      L->ws_len = 0;
+    }
+    term_items.clear();
+    gf.clear();
+    gt.clear();
+    vlen = tws_f = tws_t = 0;
+    pair_len = PW;
+    for (auto& row : coef)
+      for (auto& v : row) v.clear();
+    small.clear();
+    small4.clear();
+    is_small.clear();
+    feats.clear();
+    near = false;
+    direct.clear();
+    dpptr.clear();
+    dpairs.clear();
+  }
 };
 
 constexpr int NEAR_MAX = 256;
@@ -1383,11 +1492,14 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     const double t0 = now_seconds();
     symbolic(c);
     c.st.t_host[0] += now_seconds() - t0;
+    c.st.n_terms = int64_t(c.sym.size());
+    c.st.n_leaf_pairs = int64_t(c.hrho.size() / 3);
   }
   c.b_parent.upload(t->b_parent, s);
   c.b_dfs.upload(c.dfs.dfs_of_block, s);
   c.d_dfs_block.upload(c.dfs.dfs_block, s);
   c.group_ptr.upload(c.group_ptr_h, s);
+  c.hterms.swap(plan_arena().hterms);
   c.hterms.assign(c.sym.size(), Term{});
   c.tv = TreeView{t->dev->c_begin.p, t->dev->c_size.p, t->dev->c_parent.p, t->dev->leaf_clusters.p,
                   t->dev->b_tau.p, t->dev->b_sigma.p, t->dev->b_kind.p, c.b_parent.p, c.b_dfs.p,
@@ -1499,6 +1611,7 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     }
     return parts;
   };
+  std::vector<std::unique_ptr<Chunk>> spare_chunks;  // finished chunks, reused by later ones
   auto process_targets = [&](const std::vector<int32_t>& near, const std::vector<int32_t>& far) {
     struct Job {
       bool far;
@@ -1515,7 +1628,14 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     };
     std::future<std::unique_ptr<Chunk>> next;
     auto launch_build = [&](size_t k) {
-      auto ch = std::make_unique<Chunk>();
+      std::unique_ptr<Chunk> ch;
+      if (!spare_chunks.empty()) {  // reuse: host arrays keep their capacity
+        ch = std::move(spare_chunks.back());
+        spare_chunks.pop_back();
+        ch->reset();
+      } else {
+        ch = std::make_unique<Chunk>();
+      }
       ch->blocks = jobs[k].blocks;
       ch->near = !jobs[k].far;
       next = std::async(std::launch::async, build, std::move(ch), jobs[k].far && (predict || collect));
@@ -1563,6 +1683,7 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
           for (int32_t k : fo.ranks) C->features.ranks.push_back(float(k));
         }
       }
+      spare_chunks.push_back(std::move(chp));
     }
   };
 
@@ -1705,6 +1826,8 @@ void add_stats(hmat_stats& a, const hmat_stats& b) {
   a.n_cache_release += b.n_cache_release;
   a.target_passes += b.target_passes;
   a.n_near_direct += b.n_near_direct;
+  a.n_terms += b.n_terms;
+  a.n_leaf_pairs += b.n_leaf_pairs;
   a.t_near_panels += b.t_near_panels;
 }
 }  // namespace

@@ -50,7 +50,7 @@ class hmat_stats(C.Structure):
                 ("kern_flops", C.c_double * 8), ("t_host", C.c_double * 8), ("t_alloc", C.c_double),
                 ("n_malloc", C.c_int64), ("n_cache_release", C.c_int64), ("target_passes", C.c_int64),
                 ("streams_used", C.c_int32), ("pad_s", C.c_int32), ("n_near_direct", C.c_int64),
-                ("t_near_panels", C.c_double)]
+                ("t_near_panels", C.c_double), ("n_terms", C.c_int64), ("n_leaf_pairs", C.c_int64)]
 
     def as_dict(self):
         d = {}
