@@ -18,6 +18,9 @@ ARCH = "gfx950"
 COMMON = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in VGPRs: loop-carried accumulators are otherwise copied to
+    # AGPRs and back around every MFMA
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wno-unused-result", "-Wno-unused-command-line-argument",
 ]
 # per-source extra flags: the tree builder must not fuse multiply-adds

@@ -59,6 +59,11 @@ __device__ __forceinline__ void task_input(const Task& tk, const TDesc* td, cons
 // -- so accumulator register v is exactly the B operand of K-step v of the next product.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
+// v if c else 0. v is loaded unconditionally from an in-bounds (clamped) address and
+// scaled by 0 or 1, so the compiler keeps the load outside any branch and the steps of a
+// loop stay straight-line (panel values are finite).
+__device__ __forceinline__ double masked(bool c, double v) { return v * (c ? 1.0 : 0.0); }
+
 __device__ __forceinline__ dbl4 mfma4(double a, double b, dbl4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -254,17 +259,29 @@ __global__ void __launch_bounds__(64) k_leaf_reduce(const int64_t* __restrict__ 
   const int nkb = (kr + 15) >> 4;
   const int ks = (rows + 3) >> 2;
   double* T = ws + tk.tws + (mv.kpref[dfs] - mv.kpref[tk.lo]) * PW;
+  const int lic = min(li, w - 1);
+  const bool lok = li < w;
   for (int kb = 0; kb < nkb; ++kb) {
     dbl4 U = dbl4{0.0, 0.0, 0.0, 0.0};
     const int c = 16 * kb + li;
-    for (int s = 0; s < ks; ++s) {
-      const int r = 4 * s + lk;
-      double av = 0.0, bv = 0.0;
-      if (r < rows) {
-        if (c < kr) av = M[r + int64_t(c) * ldm];
-        if (li < w) bv = xident ? ((ro + r) == xc0 + li ? 1.0 : 0.0) : X[(ro + r) + int64_t(li) * ldx];
+    const bool cok = c < kr;
+    const int cc = min(c, kr - 1);
+    // groups of four K-steps: the loads of a group are issued together from clamped
+    // in-bounds addresses, then masked (steps past the end contribute zero)
+    for (int s0 = 0; s0 < ks; s0 += 4) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int rc = min(4 * (s0 + q) + lk, rows - 1);
+        av[q] = M[rc + int64_t(cc) * ldm];
+        bv[q] = xident ? 0.0 : X[(ro + rc) + int64_t(lic) * ldx];
       }
-      U = mfma4(av, bv, U);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 4 * (s0 + q) + lk;
+        const double b = xident ? ((r < rows && lok && (ro + r) == xc0 + li) ? 1.0 : 0.0) : masked(r < rows && lok, bv[q]);
+        U = mfma4(masked(cok && r < rows, av[q]), b, U);
+      }
     }
     // U[v] = T(16 kb + lk + 4v, li); T is kr x w column-major
 #pragma unroll
@@ -328,36 +345,54 @@ __global__ void __launch_bounds__(64) k_subtree_expand(const int64_t* __restrict
         const TS* P = tk.trans ? base + int64_t(k) * m : base;
         const int ldp = tk.trans ? n : m;
         const int ks = (k + 3) >> 2;
-        for (int s = 0; s < ks; ++s) {
-          const int cc = 4 * s + lk;
-          const double bv = (cc < k && li < w) ? Tm[cc + int64_t(li) * k] : 0.0;
+        const int lic = min(li, w - 1);
+        // groups of two K-steps, loads first (clamped), then masked MFMAs
+        for (int s0 = 0; s0 < ks; s0 += 2) {
+          double bv[2], av[2][4];
 #pragma unroll
-          for (int tile = 0; tile < 4; ++tile) {
-            if (tile < ntile) {
-              const int r = 16 * tile + li;
-              const double av = (cc < k && r < nr) ? P[(roff + r) + int64_t(cc) * ldp] : 0.0;
-              y[tile] = mfma4(av, bv, y[tile]);
-            }
+          for (int q = 0; q < 2; ++q) {
+            const int ccl = min(4 * (s0 + q) + lk, k - 1);
+            bv[q] = Tm[ccl + int64_t(lic) * k];
+#pragma unroll
+            for (int tile = 0; tile < 4; ++tile) av[q][tile] = P[(roff + min(16 * tile + li, nr - 1)) + int64_t(ccl) * ldp];
+          }
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int cc = 4 * (s0 + q) + lk;
+            const double b = masked(cc < k && li < w, bv[q]);
+#pragma unroll
+            for (int tile = 0; tile < 4; ++tile)
+              y[tile] = mfma4(masked(cc < k && 16 * tile + li < nr, av[q][tile]), b, y[tile]);
           }
         }
       } else {
         const int nin = tk.trans ? m : n;
         const int xo = o0 - in0;
         const int ks = (nin + 3) >> 2;
-        for (int s = 0; s < ks; ++s) {
-          const int j = 4 * s + lk;
-          double bv = 0.0;
-          if (j < nin && li < w)
-            bv = xident ? ((xo + j) == xc0 + li ? 1.0 : 0.0) : X[(xo + j) + int64_t(li) * ldx];
+        const int lic = min(li, w - 1);
+        const bool lok = li < w;
+        // D or D^T times X in groups of two K-steps: loads first (clamped), then masked
+        // MFMAs; rows past nr are masked, not branched
+        for (int s0 = 0; s0 < ks; s0 += 2) {
+          double bv[2], av[2][4];
 #pragma unroll
-          for (int tile = 0; tile < 4; ++tile) {
-            if (tile < ntile) {
-              const int r = 16 * tile + li;
-              double av = 0.0;
-              if (j < nin && r < nr)
-                av = tk.trans ? base[j + int64_t(roff + r) * m] : base[(roff + r) + int64_t(j) * m];
-              y[tile] = mfma4(av, bv, y[tile]);
+          for (int q = 0; q < 2; ++q) {
+            const int jc = min(4 * (s0 + q) + lk, nin - 1);
+            bv[q] = xident ? 0.0 : X[(xo + jc) + int64_t(lic) * ldx];
+#pragma unroll
+            for (int tile = 0; tile < 4; ++tile) {
+              const int rcl = min(16 * tile + li, nr - 1);
+              av[q][tile] = tk.trans ? double(base[jc + int64_t(roff + rcl) * m]) : double(base[(roff + rcl) + int64_t(jc) * m]);
             }
+          }
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int j = 4 * (s0 + q) + lk;
+            const bool jok = j < nin;
+            const double b = xident ? ((jok && lok && (xo + j) == xc0 + li) ? 1.0 : 0.0) : masked(jok && lok, bv[q]);
+#pragma unroll
+            for (int tile = 0; tile < 4; ++tile)
+              y[tile] = mfma4(masked(jok && 16 * tile + li < nr, av[q][tile]), b, y[tile]);
           }
         }
       }
@@ -409,59 +444,75 @@ __global__ void __launch_bounds__(64) k_term_reduce(const TermItem* __restrict__
   const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
   const int w = d.w;
   const int nkb = (kin + 15) >> 4;
+  const int nob = (kout + 15) >> 4;
   const int ks = (nin + 3) >> 2;
-  dbl4 U[4];
+  const int lic = min(li, w - 1);
+  const bool lok = li < w;
+  double* Vout = vbuf + it.voff;  // kout x w, column-major
+  // One accumulator chain per 16 columns of M, with no branches between its MFMAs:
+  // loads come from clamped in-bounds addresses and are masked, so several steps'
+  // loads are in flight together and the accumulator stays in place.
+  dbl4 V[4];
 #pragma unroll
-  for (int kb = 0; kb < 4; ++kb) U[kb] = dbl4{0.0, 0.0, 0.0, 0.0};
-  for (int s = 0; s < ks; ++s) {
-    const int r = 4 * s + lk;
-    double bv = 0.0;
-    if (r < nin && li < w) bv = d.xident ? (r == d.xcol0 + li ? 1.0 : 0.0) : d.X[r + int64_t(li) * d.ldx];
+  for (int ob = 0; ob < 4; ++ob) V[ob] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int kb = 0; kb < nkb; ++kb) {
+    const int c = 16 * kb + li;
+    const bool cok = c < kin;
+    const int cc = min(c, kin - 1);
+    dbl4 u = dbl4{0.0, 0.0, 0.0, 0.0};
+    const bool xid = d.xident != 0;
+    const double* X = d.X;
+    const int64_t ldx = d.ldx;
+    // groups of four K-steps: loads issued together from clamped addresses, then masked
+    for (int s0 = 0; s0 < ks; s0 += 4) {
+      double av[4], bv[4];
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb) {
-      if (kb < nkb) {
-        const int c = 16 * kb + li;
-        double av = 0.0;
-        if (c < kin && r < nin) av = mtr ? M[c + int64_t(r) * ldm] : M[r + int64_t(c) * ldm];
-        U[kb] = mfma4(av, bv, U[kb]);
+      for (int q = 0; q < 4; ++q) {
+        const int rc = min(4 * (s0 + q) + lk, nin - 1);
+        av[q] = mtr ? double(M[cc + int64_t(rc) * ldm]) : double(M[rc + int64_t(cc) * ldm]);
+        bv[q] = xid ? 0.0 : X[rc + int64_t(lic) * ldx];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 4 * (s0 + q) + lk;
+        const double b = xid ? ((r < nin && lok && r == d.xcol0 + li) ? 1.0 : 0.0) : masked(r < nin && lok, bv[q]);
+        u = mfma4(masked(cok && r < nin, av[q]), b, u);
+      }
+    }
+    if (T.core) {
+      // V += core[:, 16 kb : 16 kb + 16] u (transposed core for the transposed pass)
+#pragma unroll
+      for (int ob = 0; ob < 4; ++ob) {
+        if (ob < nob) {
+          const int i = 16 * ob + li;
+          const int ic = min(i, kout - 1);
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const int ccr = 16 * kb + 4 * s4 + lk;
+            const int ccc = min(ccr, kin - 1);
+            double av = d.trans ? double(T.core[ccc + int64_t(ic) * T.kl]) : double(T.core[ic + int64_t(ccc) * T.kl]);
+            av = masked(i < kout && ccr < kin, av);
+            V[ob] = mfma4(av, u[s4], V[ob]);
+          }
+        }
+      }
+    } else {
+      // kin == kout: u holds rows 16 kb + lk + 4 v of V
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * kb + lk + 4 * v;
+        if (row < kout && lok) Vout[row + int64_t(li) * kout] = u[v];
       }
     }
   }
-  double* V = vbuf + it.voff;  // kout x w, column-major
   if (T.core) {
-    const int nob = (kout + 15) >> 4;
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob) {
       if (ob < nob) {
-        dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
-        const int i = 16 * ob + li;
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) {
-          if (kb < nkb) {
-#pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) {
-              const int cc = 16 * kb + 4 * s4 + lk;
-              double av = 0.0;
-              if (i < kout && cc < kin) av = d.trans ? T.core[cc + int64_t(i) * T.kl] : T.core[i + int64_t(cc) * T.kl];
-              acc = mfma4(av, U[kb][s4], acc);
-            }
-          }
-        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = 16 * ob + lk + 4 * v;
-          if (row < kout && li < w) V[row + int64_t(li) * kout] = acc[v];
-        }
-      }
-    }
-  } else {
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb) {
-      if (kb < nkb) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = 16 * kb + lk + 4 * v;
-          if (row < kout && li < w) V[row + int64_t(li) * kout] = U[kb][v];
+          if (row < kout && lok) Vout[row + int64_t(li) * kout] = V[ob][v];
         }
       }
     }
@@ -510,17 +561,28 @@ __global__ void __launch_bounds__(64) k_gather_mfma(const RowItem* __restrict__ 
         r0 = row_lo - T.rrow0;
       }
       const int ks = (kout + 3) >> 2;
-      for (int s = 0; s < ks; ++s) {
-        const int cc = 4 * s + lk;
-        const double bv = (cc < kout && li < w) ? V[cc + int64_t(li) * kout] : 0.0;
+      const int lic = min(li, w - 1);
+      // groups of two K-steps (five loads each), loads first, then the masked MFMAs;
+      // rows past nr are masked, not branched
+      for (int s0 = 0; s0 < ks; s0 += 2) {
+        double bv[2], av[2][4];
 #pragma unroll
-        for (int tile = 0; tile < 4; ++tile) {
-          if (tile < ntile) {
-            const int r = 16 * tile + li;
-            double av = 0.0;
-            if (cc < kout && r < nr) av = ptr ? P[cc + (r0 + r) * ldp] : P[(r0 + r) + int64_t(cc) * ldp];
-            y[tile] = mfma4(av, bv, y[tile]);
+        for (int q = 0; q < 2; ++q) {
+          const int ccl = min(4 * (s0 + q) + lk, kout - 1);
+          bv[q] = V[ccl + int64_t(lic) * kout];
+#pragma unroll
+          for (int tile = 0; tile < 4; ++tile) {
+            const int rcl = min(16 * tile + li, nr - 1);
+            av[q][tile] = ptr ? double(P[ccl + (r0 + rcl) * ldp]) : double(P[(r0 + rcl) + int64_t(ccl) * ldp]);
           }
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int cc = 4 * (s0 + q) + lk;
+          const double b = masked(cc < kout && li < w, bv[q]);
+#pragma unroll
+          for (int tile = 0; tile < 4; ++tile)
+            y[tile] = mfma4(masked(cc < kout && 16 * tile + li < nr, av[q][tile]), b, y[tile]);
         }
       }
     }
