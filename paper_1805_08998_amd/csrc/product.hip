@@ -878,6 +878,9 @@ __global__ void __launch_bounds__(256) k_near_direct(const int32_t* __restrict__
   const int ntile = (m + 15) >> 4;
   const int jc = col0 + li;  // column of this lane in B operands and in the output
   const bool jok = jc < n && jc < cb0 + 64;
+  const int jcl = min(jc, min(n, cb0 + 64) - 1);  // clamped: every lane loads in bounds
+  // All loads below come from clamped in-bounds addresses and are masked, so the MFMA
+  // chains run without branches and the loads of a group are in flight together.
   dbl4 y[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) y[q] = dbl4{0.0, 0.0, 0.0, 0.0};
@@ -885,7 +888,8 @@ __global__ void __launch_bounds__(256) k_near_direct(const int32_t* __restrict__
     for (int it = tv.group_ptr[a]; it < tv.group_ptr[a + 1]; ++it) {
       const Term T = tv.terms[it];
       const int kl = T.kl, kr = T.kr;
-      const int64_t rrow = int64_t(in0 + jc - T.rrow0);  // R row of this lane's column
+      const int64_t rrow = int64_t(in0 + jcl - T.rrow0);  // R row of this lane's column
+      const int rt = T.rtrans;
       // V = core R_slab^T (kl x 16) in accumulator layout: V[ob][v] = V(16 ob + lk + 4 v, li)
       const int nob = (kl + 15) >> 4;
       dbl4 V[4];
@@ -896,14 +900,19 @@ __global__ void __launch_bounds__(256) k_near_direct(const int32_t* __restrict__
           V[ob] = dbl4{0.0, 0.0, 0.0, 0.0};
           if (ob < nob) {
             const int i = 16 * ob + li;
+            const int icl = min(i, kl - 1);
+            for (int s0 = 0; s0 < ks; s0 += 4) {
+              double av[4], bv[4];
 #pragma unroll
-            for (int st = 0; st < 16; ++st) {
-              if (st < ks) {
-                const int cc = 4 * st + lk;
-                const double av = (i < kl && cc < kr) ? T.core[i + int64_t(cc) * kl] : 0.0;
-                double bv = 0.0;
-                if (cc < kr && jok) bv = T.rtrans ? T.R[cc + rrow * T.ldr] : T.R[rrow + int64_t(cc) * T.ldr];
-                V[ob] = mfma4(av, bv, V[ob]);
+              for (int q = 0; q < 4; ++q) {
+                const int ccl = min(4 * (s0 + q) + lk, kr - 1);
+                av[q] = T.core[icl + int64_t(ccl) * kl];
+                bv[q] = rt ? T.R[ccl + rrow * T.ldr] : T.R[rrow + int64_t(ccl) * T.ldr];
+              }
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int cc = 4 * (s0 + q) + lk;
+                V[ob] = mfma4(masked(i < kl && cc < kr, av[q]), masked(cc < kr && jok, bv[q]), V[ob]);
               }
             }
           }
@@ -914,50 +923,59 @@ __global__ void __launch_bounds__(256) k_near_direct(const int32_t* __restrict__
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int cc = 16 * ob + lk + 4 * v;
-            double val = 0.0;
-            if (ob < nob && cc < kr && jok) val = T.rtrans ? T.R[cc + rrow * T.ldr] : T.R[rrow + int64_t(cc) * T.ldr];
-            V[ob][v] = val;
+            const int ccl = min(cc, kr - 1);
+            const double val = rt ? T.R[ccl + rrow * T.ldr] : T.R[rrow + int64_t(ccl) * T.ldr];
+            V[ob][v] = masked(ob < nob && cc < kr && jok, val);
           }
         }
       }
-      // y += L_tau V
+      // y += L_tau V: all four row tiles, rows past m masked
       const int64_t lr = int64_t(out0 - T.lrow0);
 #pragma unroll
-      for (int tile = 0; tile < 4; ++tile) {
-        if (tile < ntile) {
-          const int r = 16 * tile + li;
+      for (int ob = 0; ob < 4; ++ob) {
+        if (ob < nob) {
+          double av[4][4];
 #pragma unroll
-          for (int ob = 0; ob < 4; ++ob) {
-            if (ob < nob) {
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const int ccl = min(16 * ob + 4 * s4 + lk, kl - 1);
 #pragma unroll
-              for (int s4 = 0; s4 < 4; ++s4) {
-                const int cc = 16 * ob + 4 * s4 + lk;
-                const double av = (cc < kl && r < m) ? T.L[(lr + r) + int64_t(cc) * T.ldl] : 0.0;
-                y[tile] = mfma4(av, V[ob][s4], y[tile]);
-              }
-            }
+            for (int tile = 0; tile < 4; ++tile)
+              av[s4][tile] = T.L[(lr + min(16 * tile + li, m - 1)) + int64_t(ccl) * T.ldl];
+          }
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const int cc = 16 * ob + 4 * s4 + lk;
+#pragma unroll
+            for (int tile = 0; tile < 4; ++tile)
+              y[tile] = mfma4(masked(cc < kl && 16 * tile + li < m, av[s4][tile]), V[ob][s4], y[tile]);
           }
         }
       }
     }
   }
-  // dense pairs: y += A[tau, rho] B[rho, sigma][:, slab]
+  // dense pairs: y += A[tau, rho] B[rho, sigma][:, slab], two K-steps per group
   for (int p = pptr[t]; p < pptr[t + 1]; ++p) {
     const int qa = pairs[2 * p], qb = pairs[2 * p + 1];
     const int nr = tv.c_size[tv.b_sigma[qa]];
     const double* Ab = ma.pool + ma.off[qa] + rb0;  // rows of this sub-block, leading dimension mt
     const double* Bb = mb.pool + mb.off[qb];        // nr x n, column-major
     const int ks = (nr + 3) >> 2;
-    for (int st = 0; st < ks; ++st) {
-      const int cc = 4 * st + lk;
-      const double bv = (cc < nr && jok) ? Bb[cc + int64_t(jc) * nr] : 0.0;
+    for (int s0 = 0; s0 < ks; s0 += 2) {
+      double bv[2], av[2][4];
 #pragma unroll
-      for (int tile = 0; tile < 4; ++tile) {
-        if (tile < ntile) {
-          const int r = 16 * tile + li;
-          const double av = (cc < nr && r < m) ? Ab[r + int64_t(cc) * mt] : 0.0;
-          y[tile] = mfma4(av, bv, y[tile]);
-        }
+      for (int q = 0; q < 2; ++q) {
+        const int ccl = min(4 * (s0 + q) + lk, nr - 1);
+        bv[q] = Bb[ccl + int64_t(jcl) * nr];
+#pragma unroll
+        for (int tile = 0; tile < 4; ++tile) av[q][tile] = Ab[min(16 * tile + li, m - 1) + int64_t(ccl) * mt];
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int cc = 4 * (s0 + q) + lk;
+        const double b = masked(cc < nr && jok, bv[q]);
+#pragma unroll
+        for (int tile = 0; tile < 4; ++tile)
+          y[tile] = mfma4(masked(cc < nr && 16 * tile + li < m, av[q][tile]), b, y[tile]);
       }
     }
   }
