@@ -213,7 +213,7 @@ typedef struct {
   int32_t growth;      /* columns added per growth round (default 8) */
   int32_t probes;      /* probe columns of the a-posteriori check (default 8) */
   int32_t max_growth;  /* growth rounds before HMAT_ERR_NOT_CONVERGED (default 6) */
-  int32_t p_l;         /* oversampling added to a predicted rank (default 2) */
+  int32_t p_l;         /* oversampling added to a predicted rank above b0 (default 2) */
   int32_t time_kernels;/* 1: time every kernel launch with HIP events into stats */
   double delta;        /* residual target: E <= delta * eps * ||S||_F (default 0.2) */
   uint64_t seed;       /* random stream of the sketches (default 0x5eed) */

@@ -1666,7 +1666,9 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
             const int mn = std::min(c.m_of(ch.blocks[i]), c.n_of(ch.blocks[i]));
             const double pr = std::isfinite(pred[i]) ? std::ceil(double(pred[i])) : double(opts.o.b0);
             const int g = opts.o.probes;
-            int w = int(std::clamp(pr + opts.o.p_l, 1.0, double(64 - g)));
+            // a predicted rank within the plain initial width keeps that width (the plain
+            // first pass already covers it); above it the width is the prediction plus p_l
+            int w = pr <= opts.o.b0 ? opts.o.b0 : int(std::clamp(pr + opts.o.p_l, 1.0, double(64 - g)));
             // operator passes run PW columns at a time: widen the sketch as far as it
             // costs no extra pass of the sketch (w + g columns) or of the projection (w)
             const int up_s = (w + g + PW - 1) / PW * PW - g, up_p = (w + PW - 1) / PW * PW;
