@@ -596,10 +596,20 @@ void run_tasks(Ctx& c, TaskList& L, const TDesc* td, double* ws, bool expand, bo
   }
 }
 
-void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& pool_out, DevBuf<float>& pool32_out) {
-  const Tree& t = *c.t;
-  hipStream_t s = c.s;
-  // data layout in the pool
+// Term creation is split so that the host part of a subtree batch can be prepared on a
+// worker thread while the previous batch's targets run on the device:
+//   layout_terms  - data offsets of the created terms in their pool;
+//   prepare_terms - creation task lists and term descriptors (host only; its work
+//                   counters go to the CreatePrep, not to the shared statistics);
+//   execute_terms - uploads, creation kernels, float copies (device, calling thread).
+struct CreatePrep {
+  TaskList ff, fh;
+  int64_t pos = 0;
+  double kern_bytes[8] = {}, kern_flops[8] = {};
+  double alg_bytes = 0, alg_flops = 0, t_lists = 0;
+};
+
+int64_t layout_terms(Ctx& c, const std::vector<int32_t>& which) {
   int64_t pos = 0;
   for (int32_t i : which) {
     SymTerm& st = c.sym[i];
@@ -608,19 +618,27 @@ void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& poo
     else if (st.type == T_HF) st.data_off = pos, pos += int64_t(st.kl) * c.m_of(st.child);
     else st.data_off = -1;
   }
-  if (pool_out.n < size_t(std::max<int64_t>(pos, 1))) {  // callers may pass a pool sized for several calls
-    const double ta = now_seconds();
-    pool_out.alloc(size_t(std::max<int64_t>(pos, 1)));
-    c.st.t_host[4] += now_seconds() - ta;
-  }
-  double* P = pool_out.p;
+  return pos;
+}
+
+void prepare_terms(Ctx& c, const std::vector<int32_t>& which, double* P, int64_t pos, CreatePrep& pr) {
+  const Tree& t = *c.t;
   const double th0 = now_seconds();
-  // FF cores: leaf reductions R_A^T L_B written straight into the pool
-  // the host lists keep their capacity between calls of this thread (page faults otherwise)
-  static thread_local TaskList::Host ff_keep, fh_keep;
-  TaskList ff, fh;
-  ff.take(ff_keep);
-  fh.take(fh_keep);
+  pr.pos = pos;
+  for (int k = 0; k < 8; ++k) pr.kern_bytes[k] = pr.kern_flops[k] = 0;
+  pr.alg_bytes = pr.alg_flops = 0;
+  TaskList& ff = pr.ff;
+  TaskList& fh = pr.fh;
+  for (TaskList* L : {&ff, &fh}) {  // empty, keeping capacity
+    L->tasks.clear();
+    L->lpre.assign(1, 0);
+    L->rpre.assign(1, 0);
+    L->ws_len = 0;
+  }
+  auto acc = [&](int kind, const Coef& k, double w) {
+    pr.kern_bytes[kind] += k.a + k.b * w;
+    pr.kern_flops[kind] += k.f * w;
+  };
   for (int32_t i : which) {
     const SymTerm& st = c.sym[i];
     if (st.type == T_FF) {
@@ -641,9 +659,9 @@ void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& poo
         {
           const double nr = t.c_size[rho], w = tk.w;
           Coef k{8 * nr * st.kl, 8 * (nr + st.kl), 2 * nr * st.kl};
-          account(c.st, K_LEAF, k, w);
-          c.alg_bytes += k.a + k.b * w;
-          c.alg_flops += k.f * w;
+          acc(K_LEAF, k, w);
+          pr.alg_bytes += k.a + k.b * w;
+          pr.alg_flops += k.f * w;
         }
       }
     } else if (st.type == T_FH || st.type == T_HF) {
@@ -672,34 +690,14 @@ void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& poo
         {
           Coef kl, ke;
           subtree_coef(c, tk.mat, tk.q, tk.trans, kl, ke);
-          account(c.st, K_LEAF, kl, tk.w);
-          account(c.st, K_EXPAND, ke, tk.w);
-          c.alg_bytes += kl.a + kl.b * tk.w + ke.a + ke.b * tk.w;
-          c.alg_flops += (kl.f + ke.f) * tk.w;
+          acc(K_LEAF, kl, tk.w);
+          acc(K_EXPAND, ke, tk.w);
+          pr.alg_bytes += kl.a + kl.b * tk.w + ke.a + ke.b * tk.w;
+          pr.alg_flops += (kl.f + ke.f) * tk.w;
         }
       }
     }
   }
-  c.st.t_host[1] += now_seconds() - th0;
-  double tu = now_seconds();
-  if (!ff.tasks.empty()) ff.upload(s);
-  if (!fh.tasks.empty()) fh.upload(s);
-  c.st.t_host[5] += now_seconds() - tu;
-  tu = now_seconds();
-  if (!ff.tasks.empty()) run_tasks(c, ff, nullptr, P, false);
-  if (!fh.tasks.empty()) {
-    DevBuf<double> ws(size_t(std::max<int64_t>(fh.ws_len, 1)));
-    run_tasks(c, fh, nullptr, ws.p, true);
-  }
-  if (c.lowp) {
-    if (pool32_out.n < size_t(std::max<int64_t>(pos, 1))) pool32_out.alloc(size_t(std::max<int64_t>(pos, 1)));
-    if (pos) launch_to_float(P, pool32_out.p, pos, s);
-    c.register_pool(P, pos, pool32_out.p);
-  }
-  HM_CHECK_HIP(hipStreamSynchronize(s));
-  c.st.t_host[6] += now_seconds() - tu;
-  ff.give(ff_keep);
-  fh.give(fh_keep);
   // device descriptors of these terms
   for (int32_t i : which) {
     const SymTerm& st = c.sym[i];
@@ -752,6 +750,51 @@ void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& poo
       }
     }
   }
+  pr.t_lists = now_seconds() - th0;
+}
+
+void execute_terms(Ctx& c, CreatePrep& pr, double* P, DevBuf<float>& pool32_out) {
+  hipStream_t s = c.s;
+  for (int k = 0; k < 8; ++k) {
+    c.st.kern_bytes[k] += pr.kern_bytes[k];
+    c.st.kern_flops[k] += pr.kern_flops[k];
+  }
+  c.alg_bytes += pr.alg_bytes;
+  c.alg_flops += pr.alg_flops;
+  c.st.t_host[1] += pr.t_lists;
+  TaskList& ff = pr.ff;
+  TaskList& fh = pr.fh;
+  double tu = now_seconds();
+  if (!ff.tasks.empty()) ff.upload(s);
+  if (!fh.tasks.empty()) fh.upload(s);
+  c.st.t_host[5] += now_seconds() - tu;
+  tu = now_seconds();
+  if (!ff.tasks.empty()) run_tasks(c, ff, nullptr, P, false);
+  if (!fh.tasks.empty()) {
+    DevBuf<double> ws(size_t(std::max<int64_t>(fh.ws_len, 1)));
+    run_tasks(c, fh, nullptr, ws.p, true);
+  }
+  const int64_t pos = pr.pos;
+  if (c.lowp) {
+    if (pool32_out.n < size_t(std::max<int64_t>(pos, 1))) pool32_out.alloc(size_t(std::max<int64_t>(pos, 1)));
+    if (pos) launch_to_float(P, pool32_out.p, pos, s);
+    c.register_pool(P, pos, pool32_out.p);
+  }
+  HM_CHECK_HIP(hipStreamSynchronize(s));
+  c.st.t_host[6] += now_seconds() - tu;
+}
+
+// All three steps on the calling thread (terms of levels <= L0).
+void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& pool_out, DevBuf<float>& pool32_out,
+                  CreatePrep& pr) {
+  const int64_t pos = layout_terms(c, which);
+  if (pool_out.n < size_t(std::max<int64_t>(pos, 1))) {  // callers may pass a pool sized for several calls
+    const double ta = now_seconds();
+    pool_out.alloc(size_t(std::max<int64_t>(pos, 1)));
+    c.st.t_host[4] += now_seconds() - ta;
+  }
+  prepare_terms(c, which, pool_out.p, pos, pr);
+  execute_terms(c, pr, pool_out.p, pool32_out);
 }
 
 // Device descriptors of the terms in `which` (only these changed since the last call).
@@ -1696,7 +1739,8 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   DevBuf<double> global_pool;
   {
     double tc = now_seconds();
-    create_terms(c, gterms, global_pool, c.gpool32);
+    CreatePrep gprep;
+    create_terms(c, gterms, global_pool, c.gpool32, gprep);
     publish_terms(c, gterms);
     c.tv.terms = c.terms.p;
     c.st.t_restrict += now_seconds() - tc;
@@ -1733,11 +1777,23 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
       batch_pool.alloc(size_t(maxpool));
       c.st.t_host[4] += now_seconds() - ta;
     }
+    // the host part of batch k + 1 (layout, lists, descriptors) is prepared on a worker
+    // thread while batch k's targets run; its creation kernels start once batch k is done,
+    // because both batches use the same pool
+    CreatePrep preps[2];
+    auto prep_batch = [&](int k) {
+      const int64_t pos = layout_terms(c, bterms[k]);
+      prepare_terms(c, bterms[k], batch_pool.p, pos, preps[k & 1]);
+    };
+    prep_batch(0);
+    std::future<void> next_prep;
     for (int k = 0; k < nbatch; ++k) {
       double tc = now_seconds();
-      create_terms(c, bterms[k], batch_pool, c.bpool32);
+      if (k > 0) next_prep.get();
+      execute_terms(c, preps[k & 1], batch_pool.p, c.bpool32);
       publish_terms(c, bterms[k]);
       c.tv.terms = c.terms.p;
+      if (k + 1 < nbatch) next_prep = std::async(std::launch::async, prep_batch, k + 1);
       c.st.t_restrict += now_seconds() - tc;
       process_targets(bnear[k], bfar[k]);
     }
