@@ -1655,6 +1655,17 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     return parts;
   };
   std::vector<std::unique_ptr<Chunk>> spare_chunks;  // finished chunks, reused by later ones
+  // upload stream of the chunk builder (non-blocking, so that its copies overlap the work
+  // on the product's stream even when that is the null stream)
+  struct UploadStream {
+    hipStream_t s = nullptr;
+    UploadStream() { HM_CHECK_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking)); }
+    ~UploadStream() {
+      (void)hipStreamSynchronize(s);
+      forget_stream(s);
+      (void)hipStreamDestroy(s);
+    }
+  } s_up;
   auto process_targets = [&](const std::vector<int32_t>& near, const std::vector<int32_t>& far) {
     struct Job {
       bool far;
@@ -1665,8 +1676,12 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     for (auto& p : partition(near, false)) jobs.push_back(Job{false, std::move(p)});
     for (auto& p : partition(far, true)) jobs.push_back(Job{true, std::move(p)});
     c.st.t_host[2] += now_seconds() - tp;
-    auto build = [&c](std::unique_ptr<Chunk> ch, bool features) {
+    // the worker builds the next chunk's work lists and uploads them on its own stream
+    // while the device runs the current chunk
+    auto build = [&c, &s_up](std::unique_ptr<Chunk> ch, bool features) {
+      set_current_stream(s_up.s);
       build_chunk(c, *ch, features);
+      upload_chunk(*ch, s_up.s);  // each upload waits for its copy on s_up
       return ch;
     };
     std::future<std::unique_ptr<Chunk>> next;
@@ -1689,7 +1704,6 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
       std::unique_ptr<Chunk> chp = next.get();
       if (k + 1 < jobs.size()) launch_build(k + 1);
       Chunk& ch = *chp;
-      upload_chunk(ch, s);
       c.st.t_host[2] += now_seconds() - th;
       if (!jobs[k].far) {
         double tn = now_seconds();
