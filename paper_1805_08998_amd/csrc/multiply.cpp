@@ -488,26 +488,6 @@ struct TaskList {
     rpre.push_back(rpre.back() + (expand ? (t.c_lc_end[outc] - t.c_lc_begin[outc]) : 0));
   }
   int ntask() const { return int(tasks.size()); }
-  // host arrays handed between calls so that their capacity survives (the device
-  // arrays do not)
-  struct Host {
-    std::vector<Task> tasks;
-    std::vector<int64_t> lpre, rpre;
-  };
-  void take(Host& h) {
-    tasks.swap(h.tasks);
-    lpre.swap(h.lpre);
-    rpre.swap(h.rpre);
-    tasks.clear();
-    lpre.assign(1, 0);
-    rpre.assign(1, 0);
-    ws_len = 0;
-  }
-  void give(Host& h) {
-    tasks.swap(h.tasks);
-    lpre.swap(h.lpre);
-    rpre.swap(h.rpre);
-  }
   void upload(hipStream_t s) {
     d_tasks.upload(tasks, s);
     d_lpre.upload(lpre, s);
