@@ -58,7 +58,8 @@ void launch_probe_residual(CTarget* t, int nt, const CParams& p, hipStream_t s);
 // targets without room for another round (r + g > cap) as finished.
 void launch_check(CTarget* t, int nt, const CParams& p, int32_t* n_pending, hipStream_t s);
 // QR of Z, Jacobi SVD of the core, truncation: sets k and keeps W, J, sigma in core.
-void launch_core(CTarget* t, int nt, const CParams& p, hipStream_t s);
+// rmax: the largest rz among the targets (0: use the capacity)
+void launch_core(CTarget* t, int nt, const CParams& p, hipStream_t s, int rmax = 0);
 // L = Q W[:, :k] and R = Qz J[:, :k] into pool + out_off.
 void launch_write_factors(CTarget* t, int nt, const CParams& p, double* pool, hipStream_t s);
 

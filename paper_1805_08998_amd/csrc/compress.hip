@@ -154,18 +154,21 @@ void launch_check(CTarget* t, int nt, const CParams& p, int32_t* pending, hipStr
 // ---------------------------------------------------------------- core SVD + truncation
 constexpr int CAPMAX = 64;
 
+// LD (<= CAPMAX) is the largest column count rz of the launch's targets: the two LD x LD
+// work arrays live in dynamic LDS, so small cores leave room for more workgroups per CU.
 __global__ void __launch_bounds__(NT) k_core(CTarget* __restrict__ tg, int nt, int cap, double eps,
-                                             double kappa) {
+                                             double kappa, int LD) {
   __shared__ double h[CAPMAX];
   __shared__ double red[NT / 64];
-  __shared__ double M[CAPMAX * CAPMAX];  // Rz^T, column-major, ld CAPMAX
-  __shared__ double J[CAPMAX * CAPMAX];
+  extern __shared__ double dyn[];
+  double* M = dyn;            // Rz^T, column-major, ld LD
+  double* J = dyn + LD * LD;  // right rotations, ld LD
   __shared__ double sig[CAPMAX];
   __shared__ int order[CAPMAX];
   CTarget& T = tg[blockIdx.x];
-  const int n = T.n, r = T.rz;
+  const int n = T.n, r = min(T.rz, LD);  // the host sizes LD as the maximum rz
   double* Z = T.Z;
-  for (int i = threadIdx.x; i < CAPMAX * CAPMAX; i += NT) {
+  for (int i = threadIdx.x; i < LD * LD; i += NT) {
     M[i] = 0.0;
     J[i] = 0.0;
   }
@@ -176,7 +179,7 @@ __global__ void __launch_bounds__(NT) k_core(CTarget* __restrict__ tg, int nt, i
     double n0 = norm2_col(v, n, red);
     for (int pass = 0; pass < 2; ++pass) {
       dots_against(Z, n, j, v, h);
-      if (threadIdx.x < j) M[threadIdx.x * CAPMAX + j] += h[threadIdx.x];  // M(j, i) = R(i, j)
+      if (threadIdx.x < j) M[threadIdx.x * LD + j] += h[threadIdx.x];  // M(j, i) = R(i, j)
       __syncthreads();
       sub_combination(Z, n, j, h, v);
     }
@@ -185,20 +188,20 @@ __global__ void __launch_bounds__(NT) k_core(CTarget* __restrict__ tg, int nt, i
     double d = keep ? sqrt(n1) : 0.0;
     double inv = keep ? 1.0 / d : 0.0;
     for (int i = threadIdx.x; i < n; i += NT) v[i] *= inv;
-    if (threadIdx.x == 0) M[j * CAPMAX + j] = d;
+    if (threadIdx.x == 0) M[j * LD + j] = d;
     __syncthreads();
   }
   // one-sided Jacobi on the columns of M (r x r), accumulating J; wave 0 only
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     for (int i = 0; i < r; ++i)
-      if (lane < r) J[i * CAPMAX + lane] = (lane == i) ? 1.0 : 0.0;
+      if (lane < r) J[i * LD + lane] = (lane == i) ? 1.0 : 0.0;
     for (int sweep = 0; sweep < 40; ++sweep) {
       int rotated = 0;
       for (int p = 0; p < r - 1; ++p)
         for (int q = p + 1; q < r; ++q) {
-          double mp = lane < r ? M[p * CAPMAX + lane] : 0.0;
-          double mq = lane < r ? M[q * CAPMAX + lane] : 0.0;
+          double mp = lane < r ? M[p * LD + lane] : 0.0;
+          double mq = lane < r ? M[q * LD + lane] : 0.0;
           double a = wave_sum(mp * mp), b = wave_sum(mq * mq), c = wave_sum(mp * mq);
           if (fabs(c) <= 1e-15 * sqrt(a * b) || c == 0.0) continue;
           rotated = 1;
@@ -206,17 +209,17 @@ __global__ void __launch_bounds__(NT) k_core(CTarget* __restrict__ tg, int nt, i
           double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
           if (lane < r) {
-            M[p * CAPMAX + lane] = cs * mp - sn * mq;
-            M[q * CAPMAX + lane] = sn * mp + cs * mq;
-            double jp = J[p * CAPMAX + lane], jq = J[q * CAPMAX + lane];
-            J[p * CAPMAX + lane] = cs * jp - sn * jq;
-            J[q * CAPMAX + lane] = sn * jp + cs * jq;
+            M[p * LD + lane] = cs * mp - sn * mq;
+            M[q * LD + lane] = sn * mp + cs * mq;
+            double jp = J[p * LD + lane], jq = J[q * LD + lane];
+            J[p * LD + lane] = cs * jp - sn * jq;
+            J[q * LD + lane] = sn * jp + cs * jq;
           }
         }
       if (!rotated) break;
     }
     for (int j = 0; j < r; ++j) {
-      double mj = lane < r ? M[j * CAPMAX + lane] : 0.0;
+      double mj = lane < r ? M[j * LD + lane] : 0.0;
       double s2 = wave_sum(mj * mj);
       if (lane == 0) sig[j] = sqrt(s2);
     }
@@ -251,16 +254,18 @@ __global__ void __launch_bounds__(NT) k_core(CTarget* __restrict__ tg, int nt, i
   for (int idx = threadIdx.x; idx < r * r; idx += NT) {
     int j = idx / r, i = idx % r;
     int src = order[j];
-    core[idx] = M[src * CAPMAX + i];
-    core[cap * cap + idx] = J[src * CAPMAX + i];
+    core[idx] = M[src * LD + i];
+    core[cap * cap + idx] = J[src * LD + i];
   }
   for (int j = threadIdx.x; j < r; j += NT) core[2 * cap * cap + j] = sig[order[j]];
 }
 
-void launch_core(CTarget* t, int nt, const CParams& p, hipStream_t s) {
+void launch_core(CTarget* t, int nt, const CParams& p, hipStream_t s, int rmax) {
   if (nt <= 0) return;
   if (p.cap > CAPMAX) throw Error(HMAT_ERR_INTERNAL, "column capacity above 64");
-  hipLaunchKernelGGL(k_core, dim3(nt), dim3(NT), 0, s, t, nt, p.cap, p.eps, p.kappa);
+  const int ld = std::max(1, std::min(rmax > 0 ? rmax : p.cap, CAPMAX));
+  hipLaunchKernelGGL(k_core, dim3(nt), dim3(NT), size_t(2) * ld * ld * sizeof(double), s, t, nt, p.cap, p.eps,
+                     p.kappa, ld);
   HM_CHECK_HIP(hipGetLastError());
 }
 

@@ -1327,7 +1327,9 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
   double t3 = now_seconds();
   launch_check(dt.p, nt, cp, pending.p, s);
   c.timer.begin(K_COMPRESS);
-    launch_core(dt.p, nt, cp, s);
+    int rmax = 1;
+    for (const auto& T : h) rmax = std::max(rmax, T.rz);
+    launch_core(dt.p, nt, cp, s, rmax);
     c.timer.end();
   fetch();
   out.blocks.clear();
