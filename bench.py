@@ -278,10 +278,11 @@ def copy_probe():
 
 
 def product_source_hash():
-    """Hash of the apply-kernel sources: traffic figures measured on other sources are stale."""
+    """Hash of the apply-kernel sources and of the driver that sizes their launches:
+    traffic figures measured on other sources are stale."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("product.hip", "product_kernels.h"):
+    for f in ("product.hip", "product_kernels.h", "multiply.cpp"):
         with open(os.path.join(ROOT, "paper_1805_08998_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
