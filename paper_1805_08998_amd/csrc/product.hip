@@ -64,6 +64,14 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // loop stay straight-line (panel values are finite).
 __device__ __forceinline__ double masked(bool c, double v) { return v * (c ? 1.0 : 0.0); }
 
+// Panels and factors live in device global memory. Pointers read from descriptors are
+// generic, and loads through them compile to flat loads; through a global-address-space
+// pointer they are global loads.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+
 __device__ __forceinline__ dbl4 mfma4(double a, double b, dbl4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -223,6 +231,70 @@ __device__ __forceinline__ int find_owner(const int64_t* __restrict__ pre, int n
   return lo;
 }
 
+// u = M[:, 16 kb : 16 kb + 16]^T X for one 16-column block of M (element (r, c) of the block
+// at r * msr + mcol, lane column c) and X's column li (Xg points at it). Groups of four
+// K-steps: the loads of a group are issued together from clamped in-bounds addresses, then
+// masked. XID: X is the identity shifted by xcol0 (no X loads; Xg unused).
+template <bool XID, class TS>
+__device__ __forceinline__ dbl4 reduce_rows(const __attribute__((address_space(1))) TS* Mg, int64_t msr, int64_t mcol,
+                                            const __attribute__((address_space(1))) double* Xg, int nin, int ks,
+                                            int lk, int li, bool cok, bool lok, int xcol0) {
+  dbl4 u = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int s0 = 0; s0 < ks; s0 += 4) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int rc = min(4 * (s0 + q) + lk, nin - 1);
+      av[q] = double(Mg[int64_t(rc) * msr + mcol]);
+      if constexpr (!XID) bv[q] = Xg[rc];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = 4 * (s0 + q) + lk;
+      double b;
+      if constexpr (XID) b = (r < nin && lok && r == xcol0 + li) ? 1.0 : 0.0;
+      else b = masked(r < nin && lok, bv[q]);
+      u = mfma4(masked(cok && r < nin, av[q]), b, u);
+    }
+  }
+  return u;
+}
+
+// y[tile] += D[roff + 16 tile + li, :] X for a dense leaf D (element (i, j) at
+// i * dsr + j * dsj: rows of D, or of D^T for the transposed product), nin columns, X's
+// column li at Xg. Groups of two K-steps: loads first (clamped), then masked MFMAs; rows
+// past nr are masked, not branched. XID: X is the identity shifted by xoff (no X loads).
+template <bool XID, class TS>
+__device__ __forceinline__ void expand_dense(dbl4 (&y)[4], const __attribute__((address_space(1))) TS* Dg, int64_t dsr,
+                                             int64_t dsj, int roff, int nr,
+                                             const __attribute__((address_space(1))) double* Xg, int nin, int lk,
+                                             int li, bool lok, int xoff) {
+  const int ks = (nin + 3) >> 2;
+  for (int s0 = 0; s0 < ks; s0 += 2) {
+    double bv[2], av[2][4];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int jc = min(4 * (s0 + q) + lk, nin - 1);
+      if constexpr (!XID) bv[q] = Xg[jc];
+#pragma unroll
+      for (int tile = 0; tile < 4; ++tile) {
+        const int rcl = min(16 * tile + li, nr - 1);
+        av[q][tile] = double(Dg[int64_t(roff + rcl) * dsr + int64_t(jc) * dsj]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int j = 4 * (s0 + q) + lk;
+      const bool jok = j < nin;
+      double b;
+      if constexpr (XID) b = (jok && lok && j == xoff + li) ? 1.0 : 0.0;
+      else b = masked(jok && lok, bv[q]);
+#pragma unroll
+      for (int tile = 0; tile < 4; ++tile) y[tile] = mfma4(masked(jok && 16 * tile + li < nr, av[q][tile]), b, y[tile]);
+    }
+  }
+}
+
 template <class TS>
 __global__ void __launch_bounds__(64) k_leaf_reduce(const int64_t* __restrict__ pre, int ntask, int64_t g0,
                                                    const Task* __restrict__ tasks, const TDesc* __restrict__ td,
@@ -262,27 +334,13 @@ __global__ void __launch_bounds__(64) k_leaf_reduce(const int64_t* __restrict__ 
   const int lic = min(li, w - 1);
   const bool lok = li < w;
   for (int kb = 0; kb < nkb; ++kb) {
-    dbl4 U = dbl4{0.0, 0.0, 0.0, 0.0};
     const int c = 16 * kb + li;
     const bool cok = c < kr;
     const int cc = min(c, kr - 1);
-    // groups of four K-steps: the loads of a group are issued together from clamped
-    // in-bounds addresses, then masked (steps past the end contribute zero)
-    for (int s0 = 0; s0 < ks; s0 += 4) {
-      double av[4], bv[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int rc = min(4 * (s0 + q) + lk, rows - 1);
-        av[q] = M[rc + int64_t(cc) * ldm];
-        bv[q] = xident ? 0.0 : X[(ro + rc) + int64_t(lic) * ldx];
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = 4 * (s0 + q) + lk;
-        const double b = xident ? ((r < rows && lok && (ro + r) == xc0 + li) ? 1.0 : 0.0) : masked(r < rows && lok, bv[q]);
-        U = mfma4(masked(cok && r < rows, av[q]), b, U);
-      }
-    }
+    const dbl4 U = xident ? reduce_rows<true>(gmem(M), 1, int64_t(cc) * ldm, gmem(X), rows, ks, lk, li, cok, lok,
+                                              xc0 - ro)
+                          : reduce_rows<false>(gmem(M), 1, int64_t(cc) * ldm, gmem(X + ro + int64_t(lic) * ldx), rows,
+                                               ks, lk, li, cok, lok, 0);
     // U[v] = T(16 kb + lk + 4v, li); T is kr x w column-major
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -346,15 +404,17 @@ __global__ void __launch_bounds__(64) k_subtree_expand(const int64_t* __restrict
         const int ldp = tk.trans ? n : m;
         const int ks = (k + 3) >> 2;
         const int lic = min(li, w - 1);
+        const auto Tg = gmem(Tm + int64_t(lic) * k);
+        const auto Pg = gmem(P + roff);
         // groups of two K-steps, loads first (clamped), then masked MFMAs
         for (int s0 = 0; s0 < ks; s0 += 2) {
           double bv[2], av[2][4];
 #pragma unroll
           for (int q = 0; q < 2; ++q) {
             const int ccl = min(4 * (s0 + q) + lk, k - 1);
-            bv[q] = Tm[ccl + int64_t(lic) * k];
+            bv[q] = Tg[ccl];
 #pragma unroll
-            for (int tile = 0; tile < 4; ++tile) av[q][tile] = P[(roff + min(16 * tile + li, nr - 1)) + int64_t(ccl) * ldp];
+            for (int tile = 0; tile < 4; ++tile) av[q][tile] = double(Pg[min(16 * tile + li, nr - 1) + int64_t(ccl) * ldp]);
           }
 #pragma unroll
           for (int q = 0; q < 2; ++q) {
@@ -366,35 +426,17 @@ __global__ void __launch_bounds__(64) k_subtree_expand(const int64_t* __restrict
           }
         }
       } else {
+        // D X (or D^T X): D is m x n column-major
         const int nin = tk.trans ? m : n;
         const int xo = o0 - in0;
-        const int ks = (nin + 3) >> 2;
         const int lic = min(li, w - 1);
         const bool lok = li < w;
-        // D or D^T times X in groups of two K-steps: loads first (clamped), then masked
-        // MFMAs; rows past nr are masked, not branched
-        for (int s0 = 0; s0 < ks; s0 += 2) {
-          double bv[2], av[2][4];
-#pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            const int jc = min(4 * (s0 + q) + lk, nin - 1);
-            bv[q] = xident ? 0.0 : X[(xo + jc) + int64_t(lic) * ldx];
-#pragma unroll
-            for (int tile = 0; tile < 4; ++tile) {
-              const int rcl = min(16 * tile + li, nr - 1);
-              av[q][tile] = tk.trans ? double(base[jc + int64_t(roff + rcl) * m]) : double(base[(roff + rcl) + int64_t(jc) * m]);
-            }
-          }
-#pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            const int j = 4 * (s0 + q) + lk;
-            const bool jok = j < nin;
-            const double b = xident ? ((jok && lok && (xo + j) == xc0 + li) ? 1.0 : 0.0) : masked(jok && lok, bv[q]);
-#pragma unroll
-            for (int tile = 0; tile < 4; ++tile)
-              y[tile] = mfma4(masked(jok && 16 * tile + li < nr, av[q][tile]), b, y[tile]);
-          }
-        }
+        const int64_t dsr = tk.trans ? int64_t(m) : 1, dsj = tk.trans ? 1 : int64_t(m);
+        if (xident)
+          expand_dense<true>(y, gmem(base), dsr, dsj, roff, nr, gmem(X), nin, lk, li, lok, xc0 - xo);
+        else
+          expand_dense<false>(y, gmem(base), dsr, dsj, roff, nr, gmem(X + xo + int64_t(lic) * ldx), nin, lk, li, lok,
+                              0);
       }
     }
     if (a == outc) break;
@@ -459,28 +501,17 @@ __global__ void __launch_bounds__(64) k_term_reduce(const TermItem* __restrict__
     const int c = 16 * kb + li;
     const bool cok = c < kin;
     const int cc = min(c, kin - 1);
-    dbl4 u = dbl4{0.0, 0.0, 0.0, 0.0};
-    const bool xid = d.xident != 0;
-    const double* X = d.X;
-    const int64_t ldx = d.ldx;
-    // groups of four K-steps: loads issued together from clamped addresses, then masked
-    for (int s0 = 0; s0 < ks; s0 += 4) {
-      double av[4], bv[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int rc = min(4 * (s0 + q) + lk, nin - 1);
-        av[q] = mtr ? double(M[cc + int64_t(rc) * ldm]) : double(M[rc + int64_t(cc) * ldm]);
-        bv[q] = xid ? 0.0 : X[rc + int64_t(lic) * ldx];
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = 4 * (s0 + q) + lk;
-        const double b = xid ? ((r < nin && lok && r == d.xcol0 + li) ? 1.0 : 0.0) : masked(r < nin && lok, bv[q]);
-        u = mfma4(masked(cok && r < nin, av[q]), b, u);
-      }
-    }
+    dbl4 u;
+    // element (r, c) of M at r * msr + mcol
+    const int64_t msr = mtr ? int64_t(ldm) : 1, mcol = mtr ? int64_t(cc) : int64_t(cc) * ldm;
+    if (d.xident)
+      u = reduce_rows<true>(gmem(M), msr, mcol, gmem(Vout), nin, ks, lk, li, cok, lok, d.xcol0);
+    else
+      u = reduce_rows<false>(gmem(M), msr, mcol, gmem(d.X + int64_t(lic) * d.ldx), nin, ks, lk, li, cok, lok, 0);
     if (T.core) {
       // V += core[:, 16 kb : 16 kb + 16] u (transposed core for the transposed pass)
+      const auto Cg = gmem(T.core);
+      const int64_t csr = d.trans ? 1 : T.kl, csc = d.trans ? T.kl : 1;
 #pragma unroll
       for (int ob = 0; ob < 4; ++ob) {
         if (ob < nob) {
@@ -490,7 +521,7 @@ __global__ void __launch_bounds__(64) k_term_reduce(const TermItem* __restrict__
           for (int s4 = 0; s4 < 4; ++s4) {
             const int ccr = 16 * kb + 4 * s4 + lk;
             const int ccc = min(ccr, kin - 1);
-            double av = d.trans ? double(T.core[ccc + int64_t(ic) * T.kl]) : double(T.core[ic + int64_t(ccc) * T.kl]);
+            double av = double(Cg[int64_t(ccc) * csr + int64_t(ic) * csc]);
             av = masked(i < kout && ccr < kin, av);
             V[ob] = mfma4(av, u[s4], V[ob]);
           }
@@ -562,6 +593,10 @@ __global__ void __launch_bounds__(64) k_gather_mfma(const RowItem* __restrict__ 
       }
       const int ks = (kout + 3) >> 2;
       const int lic = min(li, w - 1);
+      // element (row, col) of P at row * psr + col * psc
+      const int64_t psr = ptr ? int64_t(ldp) : 1, psc = ptr ? 1 : int64_t(ldp);
+      const auto Pg = gmem(P + r0 * psr);
+      const auto Vg = gmem(V + int64_t(lic) * kout);
       // groups of two K-steps (five loads each), loads first, then the masked MFMAs;
       // rows past nr are masked, not branched
       for (int s0 = 0; s0 < ks; s0 += 2) {
@@ -569,11 +604,11 @@ __global__ void __launch_bounds__(64) k_gather_mfma(const RowItem* __restrict__ 
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           const int ccl = min(4 * (s0 + q) + lk, kout - 1);
-          bv[q] = V[ccl + int64_t(lic) * kout];
+          bv[q] = Vg[ccl];
 #pragma unroll
           for (int tile = 0; tile < 4; ++tile) {
             const int rcl = min(16 * tile + li, nr - 1);
-            av[q][tile] = ptr ? double(P[ccl + (r0 + rcl) * ldp]) : double(P[(r0 + rcl) + int64_t(ccl) * ldp]);
+            av[q][tile] = double(Pg[int64_t(rcl) * psr + int64_t(ccl) * psc]);
           }
         }
 #pragma unroll
