@@ -1,6 +1,6 @@
 """Benchmark of the H-matrix product C = A B on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sphere256k|...|batched64] [--mode learned|plain|mixed]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sphere256k|...] [--mode learned|plain|mixed] [--eps E]
 
 One step is one whole product hmat_multiply(A, B, eps): every farfield block
 compressed, every nearfield block evaluated, on inputs already resident in HBM.
@@ -18,6 +18,7 @@ a stratified sample of the same workload.
 
 import argparse
 import ctypes
+import dataclasses
 import json
 import os
 import sys
@@ -199,70 +200,6 @@ def train_predictor(H, configs, names, epochs, cache=None):
                    "rank_rmse_train": rmse, "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
 
 
-def run_batched(H, args):
-    """64 independent products (n log-uniform in [4096, 65536], spheres, random
-    ellipsoids and cube surfaces, kernel pairs from {1/r, exp(-r)}, leaf 64,
-    eta 0.8, inputs at 1e-8, products at 1e-6) in one hmat_multiply_batched
-    call per step; the stream count is autotuned in the warmup call. The same
-    batch with one product at a time is timed beside it."""
-    from workloads import batched_geometries
-    t0 = time.perf_counter()
-    items = []
-    for g in batched_geometries(64, 4096, 65536, seed=0):
-        tr = H.hmat_build_tree(g["points"], 64, 0.8, 0)
-        A, _ = H.hmat_assemble(tr, g["kernel_a"], 1.0, 0.0, 1e-8)
-        B, _ = H.hmat_assemble(tr, g["kernel_b"], 1.0, 0.0, 1e-8)
-        items.append((tr, A, B, g))
-    log(f"[bench] batched: 64 products assembled in {time.perf_counter() - t0:.1f}s, "
-        f"n = {sum(g['n'] for *_, g in items)} points in total")
-    As = [x[1] for x in items]
-    Bs = [x[2] for x in items]
-
-    def step(streams):
-        st = H.hmat_stats()
-        o = H.hmat_opts_default(streams=streams)
-        o.stats = ctypes.pointer(st)
-        ts = time.perf_counter()
-        Cs, status = H.hmat_multiply_batched(As, Bs, 1e-6, o)
-        dt = time.perf_counter() - ts
-        for c in Cs:
-            if c.value:
-                H.hmat_destroy(c)
-        bad = int(np.sum(status != 0))
-        if bad:
-            codes = {int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))}
-            log(f"[bench] batched: statuses {codes}: {H.lib().hmat_last_error().decode()}")
-        return dt, st.as_dict(), bad
-
-    for i in range(max(1, args.warmup)):
-        dt, st, bad = step(0)
-        log(f"[bench] batched warmup {i}: {dt:.3f}s streams {st['streams_used']} failed {bad}")
-    times = []
-    for i in range(args.steps):
-        dt, st, bad = step(0)
-        times.append(dt)
-        log(f"[bench] batched step {i}: {dt:.3f}s streams {st['streams_used']} failed {bad}")
-    t = sum(times) / len(times)
-    dts, sst, _ = step(1)
-    log(f"[bench] one product at a time: {dts:.3f}s")
-    flops = st["flops_alg"]
-    out = {
-        "metric": "batched H×H products: effective GFLOP/s at ε=1e-6 (64 products, n ∈ [4096, 65536])",
-        "value": flops / t / 1e9, "unit": "GFLOP/s (effective)", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * t, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "batched64", "products": 64, "streams": st["streams_used"],
-                   "sequential_seconds": dts, "batched_speedup": dts / t, "alg_flops": flops,
-                   "n_far": st["n_far"], "n_near": st["n_near"], "n_not_converged": st["n_not_converged"]},
-        "roofline": None, "cpu_baseline": None,
-    }
-    print(json.dumps(out))
-    for tr, A, B, _ in items:
-        H.hmat_destroy(A)
-        H.hmat_destroy(B)
-        H.hmat_tree_destroy(tr)
-
-
 def copy_probe():
     """A plain device copy of known size (1 GiB read, 1 GiB written per launch,
     five launches), the calibration run for the HBM traffic counters."""
@@ -317,7 +254,9 @@ def main():
     ap.add_argument("--features-cache", default=None,
                     help=".npz file of predictor training features (read if present, else written)")
     ap.add_argument("--compare-steps", type=int, default=1,
-                    help="timed plain products after the learned ones (learned mode only)")
+                    help="timed plain float64 products after the learned or mixed ones")
+    ap.add_argument("--eps", type=float, default=None,
+                    help="product accuracy (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -338,9 +277,13 @@ def main():
     from paper_1805_08998_amd import hmat as H
 
     if args.workload == "batched64":
-        run_batched(H, args)
-        return
+        print("bench.py: the batched64 workload is switched off. After a first complete call, later "
+              "hmat_multiply_batched calls on this 64-product batch stopped making progress, and the cause "
+              "is not known. Small batches are covered by tests/test_gpu_batched.py.", file=sys.stderr)
+        sys.exit(2)
     w = CONFIGS[args.workload]
+    if args.eps is not None:
+        w = dataclasses.replace(w, eps=args.eps)
     model = None
     train_info = None
     if args.mode == "learned":
@@ -402,7 +345,7 @@ def main():
     C, kst, kdt = run(True)
     log(f"[bench] instrumented step: {kdt:.3f}s")
     plain = None
-    if args.mode == "learned" and args.compare_steps > 0:
+    if args.mode != "plain" and args.compare_steps > 0:
         pt = []
         for i in range(args.compare_steps):
             Cp, pst, dt = run(False, "plain")
@@ -414,7 +357,7 @@ def main():
         plain = {"seconds_per_product": tp, "gflops_effective": pst["flops_alg"] / tp / 1e9,
                  "steps": len(pt), "n_growth_rounds": pst["n_growth_rounds"],
                  "n_grown_blocks": pst["n_grown_blocks"], "sketch_columns": pst["sketch_columns"],
-                 "learned_speedup": tp / t}
+                 "speedup_over_plain": tp / t}
 
     # roofline of the dominant kernel family (largest summed launch time)
     ktime = np.array(kst["kern_time"])

@@ -167,6 +167,7 @@ void hmat_release(HMat* m);
 // ---------------------------------------------------------------- options
 struct Opts {
   hmat_opts o;
+  int concurrency = 1;  // products in flight at once (set by the batched driver)
   hipStream_t stream() const { return reinterpret_cast<hipStream_t>(o.stream); }
 };
 Opts resolve_opts(const hmat_opts* o);

@@ -855,6 +855,21 @@ struct Chunk {
   bool near = false;
   std::vector<uint8_t> direct;
   std::vector<int32_t> dpptr, dpairs;  // per direct target (chunk order): dense pairs (A block, B block)
+  // recorded on the product's stream after the chunk's last kernel when the chunk is
+  // recycled: the builder's stream waits on it before reusing or freeing the device buffers
+  hipEvent_t done = nullptr;
+  bool pending = false;
+  Chunk() = default;
+  Chunk(const Chunk&) = delete;
+  Chunk& operator=(const Chunk&) = delete;
+  ~Chunk() {
+    if (done) (void)hipEventDestroy(done);
+  }
+  void mark_done(hipStream_t s) {
+    if (!done) HM_CHECK_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    HM_CHECK_HIP(hipEventRecord(done, s));
+    pending = true;
+  }
   // empties the chunk for reuse, keeping host capacity and device buffers
   void reset() {
     blocks.clear();
@@ -1547,10 +1562,11 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   // first; this is the same order at the granularity of a batch of subtrees).
   int64_t term_budget;
   {
-    // terms of one subtree batch: at most 0.45 of the available memory and at most
-    // 16 GiB (more batches cost little; very large pools are slow to map and make
-    // the budget depend on what earlier products left in the block cache)
-    const size_t fb = dev_free_bytes();
+    // terms of one subtree batch: at most 0.45 of the available memory (shared by the
+    // products in flight) and at most 16 GiB (more batches cost little; very large pools
+    // are slow to map and make the budget depend on what earlier products left in the
+    // block cache)
+    const size_t fb = dev_free_bytes() / size_t(std::max(1, opts.concurrency));
     term_budget = opts.o.workspace_limit > 0 ? 8 * opts.o.workspace_limit
                                              : std::min<int64_t>(int64_t(0.45 * double(fb)), int64_t(16) << 30);
   }
@@ -1617,10 +1633,13 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   DevBuf<double> near_buf(size_t(std::max<int64_t>(near_len, 1)));
   // device workspace of one chunk of targets: larger chunks mean fewer, fuller launches
   // (measured: 3 GiB 6.62 s, 8 GiB 6.37 s, 16 GiB 6.31 s per 262144-point product); two
-  // chunks can be alive at once, so at most 1/16 of the available memory each
+  // chunks can be alive at once, so at most 1/16 of the available memory each, shared by
+  // the products in flight (the cache would otherwise overflow and free blocks, and a
+  // device free waits for all streams)
   const int64_t budget = opts.o.workspace_limit > 0
                              ? opts.o.workspace_limit
-                             : std::min<int64_t>(int64_t(16) << 30, int64_t(dev_free_bytes() / 16));
+                             : std::min<int64_t>(int64_t(16) << 30,
+                                                 int64_t(dev_free_bytes() / (16 * std::max(1, opts.concurrency))));
   const int cap_est = std::min(64, opts.o.b0 + opts.o.max_growth * opts.o.probes);
   std::vector<FarOut> outs;
 
@@ -1642,17 +1661,25 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     return parts;
   };
   std::vector<std::unique_ptr<Chunk>> spare_chunks;  // finished chunks, reused by later ones
-  // upload stream of the chunk builder (non-blocking, so that its copies overlap the work
-  // on the product's stream even when that is the null stream)
+  // A product alone on the device builds the next chunk on a worker thread, which uploads
+  // it on its own non-blocking stream (its copies overlap the work on the product's stream
+  // even when that is the null stream), and prepares the next subtree batch on another.
+  // Products in flight next to others (batched calls) do both on their own thread and
+  // stream: the other products keep the device busy meanwhile, and each product then uses
+  // one host thread and one stream.
+  const bool overlap = opts.concurrency <= 1;
   struct UploadStream {
     hipStream_t s = nullptr;
-    UploadStream() { HM_CHECK_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking)); }
+    explicit UploadStream(bool create) {
+      if (create) HM_CHECK_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    }
     ~UploadStream() {
+      if (!s) return;
       (void)hipStreamSynchronize(s);
       forget_stream(s);
       (void)hipStreamDestroy(s);
     }
-  } s_up;
+  } s_up(overlap);
   auto process_targets = [&](const std::vector<int32_t>& near, const std::vector<int32_t>& far) {
     struct Job {
       bool far;
@@ -1667,8 +1694,18 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     // while the device runs the current chunk
     auto build = [&c, &s_up](std::unique_ptr<Chunk> ch, bool features) {
       set_current_stream(s_up.s);
+      // a recycled chunk's buffers may still be read by its last kernels on the product's
+      // stream: uploads into them, and frees (whose events are recorded on s_up), come after
+      if (ch->pending) HM_CHECK_HIP(hipStreamWaitEvent(s_up.s, ch->done, 0));
+      ch->pending = false;
       build_chunk(c, *ch, features);
       upload_chunk(*ch, s_up.s);  // each upload waits for its copy on s_up
+      return ch;
+    };
+    auto build_here = [&c, s](std::unique_ptr<Chunk> ch, bool features) {
+      build_chunk(c, *ch, features);
+      upload_chunk(*ch, s);  // on the product's stream: after the recycled chunk's kernels
+      ch->pending = false;
       return ch;
     };
     std::future<std::unique_ptr<Chunk>> next;
@@ -1683,7 +1720,14 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
       }
       ch->blocks = jobs[k].blocks;
       ch->near = !jobs[k].far;
-      next = std::async(std::launch::async, build, std::move(ch), jobs[k].far && (predict || collect));
+      const bool features = jobs[k].far && (predict || collect);
+      if (overlap) {
+        next = std::async(std::launch::async, build, std::move(ch), features);
+      } else {
+        std::promise<std::unique_ptr<Chunk>> ready;
+        ready.set_value(build_here(std::move(ch), features));
+        next = ready.get_future();
+      }
     };
     if (!jobs.empty()) launch_build(0);
     for (size_t k = 0; k < jobs.size(); ++k) {
@@ -1729,6 +1773,7 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
           for (int32_t k : fo.ranks) C->features.ranks.push_back(float(k));
         }
       }
+      chp->mark_done(s);
       spare_chunks.push_back(std::move(chp));
     }
   };
@@ -1790,11 +1835,14 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     std::future<void> next_prep;
     for (int k = 0; k < nbatch; ++k) {
       double tc = now_seconds();
-      if (k > 0) next_prep.get();
+      if (next_prep.valid()) next_prep.get();
       execute_terms(c, preps[k & 1], batch_pool.p, c.bpool32);
       publish_terms(c, bterms[k]);
       c.tv.terms = c.terms.p;
-      if (k + 1 < nbatch) next_prep = std::async(std::launch::async, prep_batch, k + 1);
+      if (k + 1 < nbatch) {
+        if (overlap) next_prep = std::async(std::launch::async, prep_batch, k + 1);
+        else prep_batch(k + 1);
+      }
       c.st.t_restrict += now_seconds() - tc;
       process_targets(bnear[k], bfar[k]);
     }
@@ -1929,6 +1977,7 @@ hmat_status multiply_batched(HMat* const* A, HMat* const* B, int32_t count, doub
           Opts o = opts;
           o.o.stream = s;
           o.o.stats = &pst[i];
+          o.concurrency = S;
           try {
             pstat[i] = multiply(A[i], B[i], eps, o, &C[i]);
             if (pstat[i] != HMAT_OK) perr[i] = "product " + std::to_string(i) + ": " + hmat_last_error();
