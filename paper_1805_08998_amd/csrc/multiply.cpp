@@ -800,7 +800,9 @@ void publish_terms(Ctx& c, const std::vector<int32_t>& which) {
     // the same terms over the float copies (TermT<float> has the layout of TermT<double>)
     static_assert(sizeof(Term32) == sizeof(Term), "term layouts differ");
     if (c.terms32.n < c.hterms.size()) c.terms32.alloc(c.hterms.size());
-    std::vector<Term32> p32(which.size());
+    static thread_local std::vector<Term32> p32_keep;  // capacity kept: no page faults per product
+    std::vector<Term32>& p32 = p32_keep;
+    p32.resize(which.size());
     for (size_t i = 0; i < which.size(); ++i) {
       const Term& T = packed[i];
       Term32& U = p32[i];
@@ -1569,6 +1571,7 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     const size_t fb = dev_free_bytes() / size_t(std::max(1, opts.concurrency));
     term_budget = opts.o.workspace_limit > 0 ? 8 * opts.o.workspace_limit
                                              : std::min<int64_t>(int64_t(0.45 * double(fb)), int64_t(16) << 30);
+    if (c.lowp) term_budget = term_budget / 3 * 2;  // the float copies of the terms take half as much again
   }
   const int depth = t->depth;
   std::vector<int64_t> cum(depth + 2, 0);
@@ -1821,6 +1824,9 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     {
       const double ta = now_seconds();
       batch_pool.alloc(size_t(maxpool));
+      // float copies of the batches' terms: one pool of the largest batch's size, so that it
+      // is not reallocated as the batches grow
+      if (c.lowp && c.bpool32.n < size_t(maxpool)) c.bpool32.alloc(size_t(maxpool));
       c.st.t_host[4] += now_seconds() - ta;
     }
     // the host part of batch k + 1 (layout, lists, descriptors) is prepared on a worker
