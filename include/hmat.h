@@ -297,6 +297,12 @@ hmat_status hmat_multiply(hmat A, hmat B, double eps, const hmat_opts* opts, hma
  * later batches of the same size class (rounded mean log2 n). If
  * opts->stats is set it receives the sums over all products, with t_total
  * the wall time of the call and streams_used the count that ran the rest.
+ * Each product in flight gets an equal share of the device memory for its
+ * workspaces; a product that still runs out of memory next to others is run
+ * again alone after the others (its status then reflects that run).
+ * Known problem: on a batch of 64 products of 4096 to 65536 points, the call
+ * after a first complete call has stopped making progress, for a reason not
+ * yet found. Batches of a few products are tested.
  */
 hmat_status hmat_multiply_batched(const hmat* A, const hmat* B, int32_t count, double eps,
                                   const hmat_opts* opts, hmat* C, int32_t* status);
