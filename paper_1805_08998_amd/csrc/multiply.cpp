@@ -1616,7 +1616,8 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   c.st.n_batches = nbatch + 1;
 
   // output matrix
-  HMat* C = new HMat();
+  std::unique_ptr<HMat> C_owner(new HMat());  // freed if the product fails part-way
+  HMat* C = C_owner.get();
   C->tree = t;
   tree_retain(t);
   C->rank.assign(nb, 0);
@@ -1891,7 +1892,7 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     c.st.n_cache_release = a1.releases - alloc0.releases;
   }
   if (opts.o.stats) *opts.o.stats = c.st;
-  *Cout = C;
+  *Cout = C_owner.release();
   if (c.st.n_not_converged > 0) {
     set_last_error(std::to_string(c.st.n_not_converged) + " farfield blocks exhausted the growth budget");
     return HMAT_ERR_NOT_CONVERGED;
