@@ -16,6 +16,7 @@
 #include <cstring>
 #include <future>
 #include <map>
+#include <unordered_map>
 #include <memory>
 #include <mutex>
 #include <numeric>
@@ -857,6 +858,14 @@ struct Chunk {
   bool near = false;
   std::vector<uint8_t> direct;
   std::vector<int32_t> dpptr, dpairs;  // per direct target (chunk order): dense pairs (A block, B block)
+  // Forward stage 1 of a pair, B[rho, sigma] X, depends only on the pair block and on X, and
+  // in a forward pass X is fixed by sigma (rows of Omega, or identity columns, at a column
+  // offset common to the pass). One stage-1 task per pair block serves all targets that hold
+  // it; its pass descriptor is entry nt + g, the widest of its targets' descriptors.
+  std::vector<int32_t> g_ptr, g_mem;  // CSR: targets of stage-1 group g
+  std::vector<Coef> g_leaf, g_exp;    // work of group g's task (per column)
+  std::vector<Coef> s1_leaf, s1_exp;  // per target: its stage-1 work as if run alone
+  std::vector<TDesc> tdx;             // pass descriptors of the targets, then of the groups
   // recorded on the product's stream after the chunk's last kernel when the chunk is
   // recycled: the builder's stream waits on it before reusing or freeing the device buffers
   hipEvent_t done = nullptr;
@@ -898,6 +907,12 @@ struct Chunk {
     direct.clear();
     dpptr.clear();
     dpairs.clear();
+    g_ptr.clear();
+    g_mem.clear();
+    g_leaf.clear();
+    g_exp.clear();
+    s1_leaf.clear();
+    s1_exp.clear();
   }
 };
 
@@ -940,7 +955,7 @@ int64_t target_cost(const Ctx& c, int32_t b, bool far, const Opts& o, int cap) {
   int64_t pr = 0;
   for (int32_t j = c.hptr[b]; j < c.hptr[b + 1]; ++j) {
     int32_t rho = c.hrho[3 * j], qa = c.hrho[3 * j + 1], qb = c.hrho[3 * j + 2];
-    pr += (t.c_size[rho] + std::max(m, n)) * PW;
+    pr += (2 * t.c_size[rho] + std::max(m, n)) * PW;
     pr += 2 * (c.da.hkpref[c.dfs.hi[qa]] - c.da.hkpref[c.dfs.lo[qa]] + c.db.hkpref[c.dfs.hi[qb]] -
                c.db.hkpref[c.dfs.lo[qb]]) * PW;
   }
@@ -962,6 +977,13 @@ void build_chunk(const Ctx& c, Chunk& ch, bool features) {
   ch.direct.assign(nt, 0);
   ch.dpptr.assign(1, 0);
   ch.dpairs.clear();
+  ch.s1_leaf.assign(nt, Coef{});
+  ch.s1_exp.assign(nt, Coef{});
+  ch.g_leaf.clear();
+  ch.g_exp.clear();
+  std::unordered_map<int32_t, int32_t> group_of;  // pair block B[rho, sigma] -> stage-1 group
+  std::vector<int64_t> group_off;                 // its temporary
+  std::vector<std::pair<int32_t, int32_t>> members;
   for (int i = 0; i < nt; ++i) {
     const int32_t b = ch.blocks[i];
     TInfo& ti = ch.info[i];
@@ -1022,17 +1044,17 @@ void build_chunk(const Ctx& c, Chunk& ch, bool features) {
         ch.dpairs.push_back(qb);
         continue;
       }
-      subtree_coef(c, 1, qb, 0, ch.coef[K_LEAF][0][i], ch.coef[K_EXPAND][0][i]);
+      subtree_coef(c, 1, qb, 0, ch.s1_leaf[i], ch.s1_exp[i]);
       subtree_coef(c, 0, qa, 0, ch.coef[K_LEAF][0][i], ch.coef[K_EXPAND][0][i]);
       subtree_coef(c, 0, qa, 1, ch.coef[K_LEAF][1][i], ch.coef[K_EXPAND][1][i]);
       subtree_coef(c, 1, qb, 1, ch.coef[K_LEAF][1][i], ch.coef[K_EXPAND][1][i]);
-      const int64_t off1 = ch.pair_len;
+      const int64_t off1 = ch.pair_len;  // transposed stage 1 (per pair)
       ch.pair_len += int64_t(t.c_size[rho]) * PW;
       const int64_t off2 = ch.pair_len;
       ch.pair_len += int64_t(std::max(m, n)) * PW;
       ch.pairs.push_back(HPair{reinterpret_cast<double*>(off2)});  // offset, rebased on upload
       auto stage = [&](TaskList& L, int64_t& tws, int mat, int32_t q, int trans, int64_t xoff, int64_t yoff,
-                       int ldy) {
+                       int ldy, int32_t tdi) {
         Task tk{};
         tk.X = xoff < 0 ? nullptr : reinterpret_cast<double*>(xoff);
         tk.ldx = t.c_size[rho];
@@ -1041,18 +1063,29 @@ void build_chunk(const Ctx& c, Chunk& ch, bool features) {
         tk.mat = mat;
         tk.q = q;
         tk.trans = trans;
-        tk.t = i;
+        tk.t = tdi;
         tk.lo = c.dfs.lo[q];
         tk.tws = tws;
         tws += subtree_ws(c, mat, q);
         L.add(c, tk, true);
       };
-      // forward: B[rho, sigma] X -> temp1, then A[tau, rho] temp1 -> temp2
-      stage(ch.t1f, ch.tws_f, 1, qb, 0, -1, off1, t.c_size[rho]);
-      stage(ch.t2f, ch.tws_f, 0, qa, 0, off1, off2, m);
+      // forward: B[rho, sigma] X -> temp1 of the pair block's group, then A[tau, rho] temp1 -> temp2
+      auto gi = group_of.find(qb);
+      if (gi == group_of.end()) {
+        const int32_t g = int32_t(group_off.size());
+        gi = group_of.emplace(qb, g).first;
+        group_off.push_back(ch.pair_len);
+        ch.pair_len += int64_t(t.c_size[rho]) * PW;
+        ch.g_leaf.emplace_back();
+        ch.g_exp.emplace_back();
+        subtree_coef(c, 1, qb, 0, ch.g_leaf.back(), ch.g_exp.back());
+        stage(ch.t1f, ch.tws_f, 1, qb, 0, -1, group_off[g], t.c_size[rho], nt + g);
+      }
+      members.emplace_back(gi->second, i);
+      stage(ch.t2f, ch.tws_f, 0, qa, 0, group_off[gi->second], off2, m, i);
       // transposed: A[tau, rho]^T X -> temp1, then B[rho, sigma]^T temp1 -> temp2
-      stage(ch.t1t, ch.tws_t, 0, qa, 1, -1, off1, t.c_size[rho]);
-      stage(ch.t2t, ch.tws_t, 1, qb, 1, off1, off2, n);
+      stage(ch.t1t, ch.tws_t, 0, qa, 1, -1, off1, t.c_size[rho], i);
+      stage(ch.t2t, ch.tws_t, 1, qb, 1, off1, off2, n, i);
     }
     ti.hp_end = int32_t(ch.pairs.size());
     if (direct) {
@@ -1063,6 +1096,16 @@ void build_chunk(const Ctx& c, Chunk& ch, bool features) {
       add_subtree_rows(t, i, tau, ch.gf);
       add_subtree_rows(t, i, sig, ch.gt);
     }
+  }
+  // members of each stage-1 group (CSR, targets in chunk order)
+  const int32_t ng = int32_t(group_off.size());
+  ch.g_ptr.assign(size_t(ng) + 1, 0);
+  for (const auto& gm : members) ch.g_ptr[gm.first + 1]++;
+  for (int32_t g = 0; g < ng; ++g) ch.g_ptr[g + 1] += ch.g_ptr[g];
+  ch.g_mem.resize(members.size());
+  {
+    std::vector<int32_t> fill(ch.g_ptr.begin(), ch.g_ptr.end() - 1);
+    for (const auto& gm : members) ch.g_mem[fill[gm.first]++] = gm.second;
   }
 }
 
@@ -1087,16 +1130,34 @@ void upload_chunk(Chunk& ch, hipStream_t s) {
   ch.vbuf.alloc(size_t(std::max<int64_t>(ch.vlen, 1)));
   ch.wsf.alloc(size_t(std::max<int64_t>(ch.tws_f, 1)));
   ch.wst.alloc(size_t(std::max<int64_t>(ch.tws_t, 1)));
-  ch.d_td.alloc(ch.blocks.size());
+  ch.d_td.alloc(ch.blocks.size() + ch.g_leaf.size());
 }
 
 // One application of every target's operator in the chunk (forward: S X, transposed: S^T X).
 void run_pass(Ctx& c, Chunk& ch, const std::vector<TDesc>& td, bool trans, bool lowp = false) {
   hipStream_t s = c.s;
-  ch.d_td.upload(td, s);  // synchronous: td is rewritten for the next pass
+  // descriptors of the targets, then of the stage-1 groups (forward passes): a group takes
+  // the descriptor of its widest target (same X for all of them; the others read a prefix
+  // of the columns)
+  const size_t nt = td.size(), ngr = ch.g_leaf.size();
+  ch.tdx.assign(td.begin(), td.end());
+  ch.tdx.resize(nt + ngr);
+  for (size_t g = 0; g < ngr; ++g) {
+    TDesc& e = ch.tdx[nt + g];
+    std::memset(&e, 0, sizeof(e));
+    if (trans) continue;
+    for (int32_t k = ch.g_ptr[g]; k < ch.g_ptr[g + 1]; ++k)
+      if (td[ch.g_mem[k]].w > e.w) e = td[ch.g_mem[k]];
+    e.Y = nullptr;  // stage 1 writes the group's temporary
+    if (e.w) {
+      account(c.st, K_LEAF, ch.g_leaf[g], e.w);
+      account(c.st, K_EXPAND, ch.g_exp[g], e.w);
+    }
+  }
+  ch.d_td.upload(ch.tdx, s);  // synchronous: the descriptors are rewritten for the next pass
   const TDesc* dtd = ch.d_td.p;
   const int d = trans ? 1 : 0;
-  for (size_t i = 0; i < td.size(); ++i)
+  for (size_t i = 0; i < nt; ++i)
     if (td[i].w) {
       c.st.target_passes++;
       account(c.st, K_LEAF, ch.coef[K_LEAF][d][i], td[i].w);
@@ -1374,6 +1435,10 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
         c.alg_bytes += cf.a + cf.b * w;
         c.alg_flops += cf.f * w;
       }
+    for (const Coef* cf : {&ch.s1_leaf[i], &ch.s1_exp[i]}) {  // forward stage 1, counted per target
+      c.alg_bytes += cf->a + cf->b * w;
+      c.alg_flops += cf->f * w;
+    }
     c.alg_flops += 4.0 * (T.m + T.n) * w * w + 22.0 * w * w * w;
     c.alg_bytes += 8.0 * (T.m + T.n) * T.k;
   }
@@ -1477,6 +1542,10 @@ void evaluate_chunk(Ctx& c, Chunk& ch, double* cpool, const std::vector<int64_t>
       const Coef& cf = ch.coef[k][0][i];
       c.alg_bytes += cf.a + cf.b * w;
       c.alg_flops += cf.f * w;
+    }
+    for (const Coef* cf : {&ch.s1_leaf[i], &ch.s1_exp[i]}) {  // forward stage 1, counted per target
+      c.alg_bytes += cf->a + cf->b * w;
+      c.alg_flops += cf->f * w;
     }
   }
   HM_CHECK_HIP(hipStreamSynchronize(c.s));
