@@ -1753,60 +1753,69 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
       (void)hipStreamDestroy(s);
     }
   } s_up(overlap);
-  auto process_targets = [&](const std::vector<int32_t>& near, const std::vector<int32_t>& far) {
-    struct Job {
-      bool far;
-      std::vector<int32_t> blocks;
-    };
+  struct Job {
+    bool far;
+    std::vector<int32_t> blocks;
+  };
+  auto make_jobs = [&](const std::vector<int32_t>& near, const std::vector<int32_t>& far) {
     std::vector<Job> jobs;
     const double tp = now_seconds();
     for (auto& p : partition(near, false)) jobs.push_back(Job{false, std::move(p)});
     for (auto& p : partition(far, true)) jobs.push_back(Job{true, std::move(p)});
     c.st.t_host[2] += now_seconds() - tp;
-    // the worker builds the next chunk's work lists and uploads them on its own stream
-    // while the device runs the current chunk
-    auto build = [&c, &s_up](std::unique_ptr<Chunk> ch, bool features) {
-      set_current_stream(s_up.s);
-      // a recycled chunk's buffers may still be read by its last kernels on the product's
-      // stream: uploads into them, and frees (whose events are recorded on s_up), come after
-      if (ch->pending) HM_CHECK_HIP(hipStreamWaitEvent(s_up.s, ch->done, 0));
-      ch->pending = false;
-      build_chunk(c, *ch, features);
-      upload_chunk(*ch, s_up.s);  // each upload waits for its copy on s_up
-      return ch;
-    };
-    auto build_here = [&c, s](std::unique_ptr<Chunk> ch, bool features) {
-      build_chunk(c, *ch, features);
-      upload_chunk(*ch, s);  // on the product's stream: after the recycled chunk's kernels
-      ch->pending = false;
-      return ch;
-    };
-    std::future<std::unique_ptr<Chunk>> next;
-    auto launch_build = [&](size_t k) {
-      std::unique_ptr<Chunk> ch;
-      if (!spare_chunks.empty()) {  // reuse: host arrays keep their capacity
-        ch = std::move(spare_chunks.back());
-        spare_chunks.pop_back();
-        ch->reset();
-      } else {
-        ch = std::make_unique<Chunk>();
-      }
-      ch->blocks = jobs[k].blocks;
-      ch->near = !jobs[k].far;
-      const bool features = jobs[k].far && (predict || collect);
-      if (overlap) {
-        next = std::async(std::launch::async, build, std::move(ch), features);
-      } else {
-        std::promise<std::unique_ptr<Chunk>> ready;
-        ready.set_value(build_here(std::move(ch), features));
-        next = ready.get_future();
-      }
-    };
-    if (!jobs.empty()) launch_build(0);
+    return jobs;
+  };
+  // the worker builds the next chunk's work lists and uploads them on its own stream
+  // while the device runs the current chunk
+  auto build = [&c, &s_up](std::unique_ptr<Chunk> ch, bool features) {
+    set_current_stream(s_up.s);
+    // a recycled chunk's buffers may still be read by its last kernels on the product's
+    // stream: uploads into them, and frees (whose events are recorded on s_up), come after
+    if (ch->pending) HM_CHECK_HIP(hipStreamWaitEvent(s_up.s, ch->done, 0));
+    ch->pending = false;
+    build_chunk(c, *ch, features);
+    upload_chunk(*ch, s_up.s);  // each upload waits for its copy on s_up
+    return ch;
+  };
+  auto build_here = [&c, s](std::unique_ptr<Chunk> ch, bool features) {
+    build_chunk(c, *ch, features);
+    upload_chunk(*ch, s);  // on the product's stream: after the recycled chunk's kernels
+    ch->pending = false;
+    return ch;
+  };
+  // the chunk being built; declared after s_up so that a pending build ends before s_up does
+  std::future<std::unique_ptr<Chunk>> next;
+  auto launch_build = [&](const Job& job) {
+    std::unique_ptr<Chunk> ch;
+    if (!spare_chunks.empty()) {  // reuse: host arrays keep their capacity
+      ch = std::move(spare_chunks.back());
+      spare_chunks.pop_back();
+      ch->reset();
+    } else {
+      ch = std::make_unique<Chunk>();
+    }
+    ch->blocks = job.blocks;
+    ch->near = !job.far;
+    const bool features = job.far && (predict || collect);
+    if (overlap) {
+      next = std::async(std::launch::async, build, std::move(ch), features);
+    } else {
+      std::promise<std::unique_ptr<Chunk>> ready;
+      ready.set_value(build_here(std::move(ch), features));
+      next = ready.get_future();
+    }
+  };
+  // Runs the chunks of `jobs`. With `then` (the jobs of the next call), the first chunk of
+  // the next call is built while the last chunk of this one runs; the next call finds it in
+  // `next`. Building reads only the plan, so it may overlap the next subtree batch's term
+  // creation.
+  auto process_targets = [&](const std::vector<Job>& jobs, const std::vector<Job>* then) {
+    if (!jobs.empty() && !next.valid()) launch_build(jobs[0]);
     for (size_t k = 0; k < jobs.size(); ++k) {
       const double th = now_seconds();
       std::unique_ptr<Chunk> chp = next.get();
-      if (k + 1 < jobs.size()) launch_build(k + 1);
+      if (k + 1 < jobs.size()) launch_build(jobs[k + 1]);
+      else if (then && !then->empty()) launch_build((*then)[0]);
       Chunk& ch = *chp;
       c.st.t_host[2] += now_seconds() - th;
       if (!jobs[k].far) {
@@ -1870,7 +1879,7 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
       if (t->b_level[b] <= L0) nf.push_back(b);
     for (int32_t b : far_all)
       if (t->b_level[b] <= L0) ff.push_back(b);
-    process_targets(nf, ff);
+    process_targets(make_jobs(nf, ff), nullptr);
   }
   // batches of deeper subtrees
   if (L0 < depth) {
@@ -1908,6 +1917,7 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
       prepare_terms(c, bterms[k], batch_pool.p, pos, preps[k & 1]);
     };
     prep_batch(0);
+    std::vector<Job> jobs_cur = make_jobs(bnear[0], bfar[0]), jobs_next;
     std::future<void> next_prep;
     for (int k = 0; k < nbatch; ++k) {
       double tc = now_seconds();
@@ -1920,7 +1930,10 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
         else prep_batch(k + 1);
       }
       c.st.t_restrict += now_seconds() - tc;
-      process_targets(bnear[k], bfar[k]);
+      if (k + 1 < nbatch) jobs_next = make_jobs(bnear[k + 1], bfar[k + 1]);
+      else jobs_next.clear();
+      process_targets(jobs_cur, overlap ? &jobs_next : nullptr);
+      jobs_cur.swap(jobs_next);
     }
   }
 
