@@ -267,7 +267,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the product runs on a "
-              "single MI355X (sharding over GPUs is described in DESIGN.md, not built)", file=sys.stderr)
+              "single MI355X (sharding the product over GPUs is not built)", file=sys.stderr)
         sys.exit(2)
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs as a single process on one GPU", file=sys.stderr)
