@@ -155,11 +155,12 @@ def cpu_baseline(H, tree, A, B, eps, flops_alg, seconds=20.0, max_rows=256, seed
     return out
 
 
-def train_predictor(H, configs, names, epochs, cache=None):
+def train_predictor(H, configs, names, epochs, cache=None, eps=None):
     """Rank predictor trained on the farfield ranks of plain products of other
-    workloads (untimed). Returns the model handle and a summary. With `cache`,
-    the training features are read from that .npz file when it exists (written
-    by an earlier run with the same option), else computed and saved there."""
+    workloads (untimed), at their own accuracy or at `eps` when given. Returns
+    the model handle and a summary. With `cache`, the training features are read
+    from that .npz file when it exists (written by an earlier run with the same
+    options), else computed and saved there."""
     feats, ranks = [], []
     t0 = time.perf_counter()
     if cache and os.path.exists(cache):
@@ -176,7 +177,7 @@ def train_predictor(H, configs, names, epochs, cache=None):
         st = H.hmat_stats()
         o = H.hmat_opts_default()
         o.stats = ctypes.pointer(st)
-        C, _ = H.hmat_multiply(A, B, wl.eps, o, allow_not_converged=True)
+        C, _ = H.hmat_multiply(A, B, wl.eps if eps is None else eps, o, allow_not_converged=True)
         f, r = H.hmat_product_features(C)
         feats.append(f)
         ranks.append(r)
@@ -196,7 +197,7 @@ def train_predictor(H, configs, names, epochs, cache=None):
     rmse = float(np.sqrt(np.mean((pred - r) ** 2)))
     log(f"[bench] predictor trained on {len(r)} blocks in {t2 - t1:.1f}s (data {t1 - t0:.1f}s), "
         f"loss {losses[0]:.4f} -> {losses[-1]:.4f}, rank rmse {rmse:.2f}")
-    return model, {"train_on": names, "samples": int(len(r)), "epochs": epochs, "train_seconds": t2 - t1,
+    return model, {"train_on": names, "train_eps": eps, "samples": int(len(r)), "epochs": epochs, "train_seconds": t2 - t1,
                    "rank_rmse_train": rmse, "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
 
 
@@ -256,7 +257,7 @@ def main():
     ap.add_argument("--compare-steps", type=int, default=1,
                     help="timed plain float64 products after the learned or mixed ones")
     ap.add_argument("--eps", type=float, default=None,
-                    help="product accuracy (default: the workload's)")
+                    help="product accuracy (default: the workload's); the predictor is then trained at it too")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -288,7 +289,7 @@ def main():
     train_info = None
     if args.mode == "learned":
         model, train_info = train_predictor(H, CONFIGS, args.train_on.split(","), args.train_epochs,
-                                            args.features_cache)
+                                            args.features_cache, eps=args.eps)
     pts = w.points()
     t0 = time.perf_counter()
     tree = H.hmat_build_tree(pts, w.leaf, w.eta, w.split)
