@@ -49,24 +49,39 @@ def leaf_arrays(H, tree):
                 level=bl["level"][ids])
 
 
-def cpu_baseline(H, tree, A, B, eps, flops_alg, seconds=20.0, max_rows=256, seed=0, C=None):
+def host_cpus():
+    """Logical CPUs of the host as lscpu reports them (None if lscpu is missing)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except Exception:
+        return None
+    for line in out.splitlines():
+        if line.startswith("CPU(s):"):
+            return int(line.split(":")[1])
+    return None
+
+
+def cpu_baseline(H, tree, A, B, C, eps, seconds=20.0, max_rows=256, seed=0):
     """The CPU oracle (exact block from densified strips of the library's A_H and
     B_H, singular values for farfield blocks) timed on a stratified sample: per
-    (level, kind) a few leaves of at most max_rows rows. The oracle's time for
-    the whole product is estimated level by level from its measured rate in
-    exact-block entries per second (levels without sample use the nearest
-    sampled level), and reported as effective GFLOP/s on the same flop count.
-    With C (the library's product), each sampled exact block is also compared
-    with C's block after the timing: relative error / eps and rank - eps-rank
-    for farfield blocks, relative error for nearfield blocks."""
+    (level, kind) a few leaves of at most max_rows rows, about `seconds` of oracle
+    time in all. Reported as measured: seconds per block for each sampled
+    (level, kind), and the effective rate on the sample, i.e. the algorithmic
+    flops the product charged to the sampled blocks (hmat_product_block_flops) /
+    the oracle's time on them. Nothing is extrapolated to the whole product.
+    Each sampled exact block is also compared with C's block after the timing:
+    relative error / eps and rank - eps-rank for farfield blocks, relative
+    error for nearfield blocks."""
     from oracle.product import LeafStrips, oracle_block
     try:
         from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     except Exception:
-        cores = os.cpu_count() or 1
+        threads = os.cpu_count() or 1
     la = leaf_arrays(H, tree)
     n = H.hmat_tree_info(tree)["n"]
+    bflops = H.hmat_product_block_flops(C)
 
     def src(M):
         def get(i):
@@ -78,17 +93,20 @@ def cpu_baseline(H, tree, A, B, eps, flops_alg, seconds=20.0, max_rows=256, seed
     parity = {"far_err": [], "slack": [], "near_err": []}
     rng = np.random.default_rng(seed)
     levels = np.unique(la["level"])
-    rates = {}
-    sampled = 0
-    t_spent = 0.0
+    per = {}
+    f_sample, t_sample, sampled = 0.0, 0.0, 0
     budget_per = seconds / max(1, 2 * len(levels))
     for L in levels[::-1]:
         for kind in (1, 2):
             cand = np.nonzero((la["level"] == L) & (la["kind"] == kind) & (la["r1"] - la["r0"] <= max_rows)
                               & (la["c1"] - la["c0"] <= max_rows))[0]
+            total = int(np.sum((la["level"] == L) & (la["kind"] == kind)))
             if cand.size == 0:
+                if total:
+                    per[f"{int(L)}/{'far' if kind == 1 else 'near'}"] = {"blocks_in_product": total,
+                                                                          "sampled": 0}
                 continue
-            ent, tt = 0.0, 0.0
+            cnt, tt, ff = 0, 0.0, 0.0
             for i in rng.permutation(cand)[:64]:
                 r0, r1, c0, c1 = la["r0"][i], la["r1"][i], la["c0"][i], la["c1"][i]
                 for j in sa.rows_needed(r0, r1):  # fetch the inputs first: only the oracle is timed
@@ -98,50 +116,41 @@ def cpu_baseline(H, tree, A, B, eps, flops_alg, seconds=20.0, max_rows=256, seed
                 ts = time.perf_counter()
                 D, sv, kstar = oracle_block(sa, sb, r0, r1, c0, c1, kind, eps)
                 dt = time.perf_counter() - ts
-                if C is not None:
-                    d, U, V = H.hmat_block_get(C, int(i))
-                    nd = float(np.linalg.norm(D))
-                    if kind == 1:
-                        e = float(np.linalg.norm(D - U @ V.T)) / max(nd, 1e-300)
-                        parity["far_err"].append(e / eps)
-                        parity["slack"].append(int(d["rank"]) - int(kstar))
-                    else:
-                        parity["near_err"].append(float(np.linalg.norm(D - V)) / max(nd, 1e-300))
-                ent += float((r1 - r0) * (c1 - c0))
+                d, U, V = H.hmat_block_get(C, int(i))
+                nd = float(np.linalg.norm(D))
+                if kind == 1:
+                    e = float(np.linalg.norm(D - U @ V.T)) / max(nd, 1e-300)
+                    parity["far_err"].append(e / eps)
+                    parity["slack"].append(int(d["rank"]) - int(kstar))
+                else:
+                    parity["near_err"].append(float(np.linalg.norm(D - V)) / max(nd, 1e-300))
+                cnt += 1
                 tt += dt
-                sampled += 1
-                t_spent += dt
+                ff += float(bflops[i])
                 sa.cache.clear()
                 sb.cache.clear()
                 if tt > budget_per:
                     break
-            rates[(int(L), kind)] = ent / tt
-    # estimated oracle time for all leaves
-    t_est = 0.0
-    keys = sorted(rates)
-    for L in levels:
-        for kind in (1, 2):
-            m = (la["level"] == L) & (la["kind"] == kind)
-            if not m.any():
-                continue
-            ents = float(((la["r1"] - la["r0"]) * (la["c1"] - la["c0"]))[m].sum())
-            key = (int(L), kind)
-            if key not in rates:
-                same = [k for k in keys if k[1] == kind] or keys
-                key = min(same, key=lambda k: abs(k[0] - L))
-            t_est += ents / rates[key]
+            per[f"{int(L)}/{'far' if kind == 1 else 'near'}"] = {
+                "blocks_in_product": total, "sampled": cnt, "seconds_per_block": tt / cnt,
+                "max_rows": int(np.max((la["r1"] - la["r0"])[cand]))}
+            f_sample += ff
+            t_sample += tt
+            sampled += cnt
     out = {
-        "value": flops_alg / t_est / 1e9,
-        "unit": "GFLOP/s (effective, same flop count as value)",
-        "cores": int(cores),
+        "value": f_sample / t_sample / 1e9,
+        "unit": "GFLOP/s (effective: algorithmic flops of the sampled blocks / oracle seconds on them)",
+        "cores": int(threads),
+        "host_cpus_lscpu": host_cpus(),
         "kind": "oracle",
-        "sample": f"{sampled} leaves (<= {max_rows} rows, per level and kind) of this workload, "
-                  f"exact blocks from densified strips of the library's A_H, B_H + SVD for farfield; "
-                  f"{t_spent:.1f} s measured, whole-product oracle time estimated at {t_est:.0f} s "
-                  f"from per-level entry rates",
-        "oracle_seconds_estimated": t_est,
+        "sample": f"{sampled} leaves of this workload (<= {max_rows} rows, up to 64 per level and kind, "
+                  f"{t_sample:.1f} s of oracle time): exact block from densified strips of the library's "
+                  f"A_H and B_H, plus the singular values of farfield blocks; one process, BLAS threads = cores",
+        "seconds_measured": t_sample,
+        "flops_of_sampled_blocks": f_sample,
+        "seconds_per_block": per,
     }
-    if C is not None and parity["far_err"]:
+    if parity["far_err"]:
         fe = np.array(parity["far_err"])
         sl = np.array(parity["slack"])
         ne = np.array(parity["near_err"]) if parity["near_err"] else np.zeros(1)
@@ -254,8 +263,8 @@ def main():
     ap.add_argument("--train-epochs", type=int, default=30)
     ap.add_argument("--features-cache", default=None,
                     help=".npz file of predictor training features (read if present, else written)")
-    ap.add_argument("--compare-steps", type=int, default=1,
-                    help="timed plain float64 products after the learned or mixed ones")
+    ap.add_argument("--compare-steps", type=int, default=None,
+                    help="timed plain float64 products after the learned or mixed ones (default: min(--steps, 5))")
     ap.add_argument("--eps", type=float, default=None,
                     help="product accuracy (default: the workload's); the predictor is then trained at it too")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -335,10 +344,14 @@ def main():
         stats.append(st)
         log(f"[bench] step {i}: {dt:.3f}s batches {st['n_batches']} restrict {st['t_restrict']:.3f} "
             f"near {st['t_near']:.3f} sketch {st['t_sketch']:.3f} project {st['t_project']:.3f} "
-            f"grown {st['n_grown_blocks']} fallback {st['n_fallback']} columns {st['sketch_columns']}")
+            f"grown {st['n_grown_blocks']} fallback {st['n_fallback']} columns {st['sketch_columns']} "
+            f"alloc {st['t_alloc']:.3f}s releases {st['n_cache_release']}")
     t = sum(times) / len(times)
     st = stats[-1]
     flops = st["flops_alg"]
+    spread = {"mean_s": t, "median_s": float(np.median(times)), "min_s": min(times), "max_s": max(times),
+              "steps": len(times), "cache_releases": int(sum(x["n_cache_release"] for x in stats)),
+              "alloc_s_max": max(x["t_alloc"] for x in stats)}
     # one more product with every kernel launch bracketed by HIP events on the
     # library's stream: per-family launch durations for the roofline (event
     # records slow the product down, so this step is not part of `value`)
@@ -346,19 +359,23 @@ def main():
     C, kst, kdt = run(True)
     log(f"[bench] instrumented step: {kdt:.3f}s")
     plain = None
-    if args.mode != "plain" and args.compare_steps > 0:
+    compare_steps = min(args.steps, 5) if args.compare_steps is None else args.compare_steps
+    if args.mode != "plain" and compare_steps > 0:
         pt = []
-        for i in range(args.compare_steps):
+        for i in range(compare_steps):
             Cp, pst, dt = run(False, "plain")
             H.hmat_destroy(Cp)
             pt.append(dt)
             log(f"[bench] plain step {i}: {dt:.3f}s batches {pst['n_batches']} grown {pst['n_grown_blocks']} "
                 f"columns {pst['sketch_columns']} sketch {pst['t_sketch']:.3f} project {pst['t_project']:.3f}")
         tp = sum(pt) / len(pt)
-        plain = {"seconds_per_product": tp, "gflops_effective": pst["flops_alg"] / tp / 1e9,
+        plain = {"seconds_per_product": tp, "median_s": float(np.median(pt)), "min_s": min(pt), "max_s": max(pt),
+                 "gflops_effective": pst["flops_alg"] / tp / 1e9,
                  "steps": len(pt), "n_growth_rounds": pst["n_growth_rounds"],
                  "n_grown_blocks": pst["n_grown_blocks"], "sketch_columns": pst["sketch_columns"],
-                 "speedup_over_plain": tp / t}
+                 "target_passes": pst["target_passes"],
+                 "speedup_over_plain_mean": tp / t,
+                 "speedup_over_plain_median": float(np.median(pt)) / float(np.median(times))}
 
     # roofline of the dominant kernel family (largest summed launch time)
     ktime = np.array(kst["kern_time"])
@@ -390,10 +407,21 @@ def main():
                                        "TFLOP_s": (kf[k] / ktime[k] / 1e12) if ktime[k] > 0 else None}
                      for k in range(8)},
     }
+    # whole product against the roofline: the floor is the larger of the algorithmic
+    # flops at the fp64 peak and the algorithmic bytes at the HBM peak; the compulsory
+    # bytes read every input panel once per operator pass (range and projection) and
+    # write the output once
+    pool_bytes = {name: 8.0 * H.hmat_pool_len(M) for name, M in (("A", A), ("B", B), ("C", C))}
+    compulsory = 2.0 * (pool_bytes["A"] + pool_bytes["B"]) + pool_bytes["C"]
+    floor = max(flops / (FP64_PEAK_TFLOPS * 1e12), st["bytes_alg"] / (HBM_PEAK_GBS * 1e9))
+    roofline["whole_product"] = {
+        "flops_alg": flops, "bytes_alg": st["bytes_alg"], "floor_s": floor, "frac": floor / t,
+        "compulsory_bytes": compulsory, "compulsory_floor_s": compulsory / (HBM_PEAK_GBS * 1e9),
+        "bytes_alg_over_compulsory": st["bytes_alg"] / compulsory, "pool_bytes": pool_bytes}
     cpu = None
     if not args.no_cpu_baseline:
         try:
-            cpu = cpu_baseline(H, tree, A, B, w.eps, flops, seconds=args.cpu_seconds, C=C)
+            cpu = cpu_baseline(H, tree, A, B, C, w.eps, seconds=args.cpu_seconds)
         except Exception as e:  # the baseline is reported, never the target
             log(f"[bench] cpu baseline failed: {e!r}")
     out = {
@@ -414,7 +442,7 @@ def main():
                    "kernels": [f"{w.kernel_a.kind}+{w.kernel_a.shift}I", f"{w.kernel_b.kind}+{w.kernel_b.shift}I"],
                    "eps": w.eps, "eps_in": w.eps_in, "mode": args.mode, "seconds_per_product": t,
                    "alg_flops": flops, "alg_bytes": st["bytes_alg"], "predictor": train_info,
-                   "plain": plain},
+                   "timing": spread, "plain": plain},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stats": {k: v for k, v in st.items() if k not in ("rank_hist",)},

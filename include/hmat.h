@@ -69,6 +69,10 @@ const char* hmat_version(void);
  * through alloc(bytes, ctx) and free(ptr, ctx) (for instance a framework's
  * caching allocator); when reset with NULL functions, hipMalloc/hipFree are
  * used. Set it before creating handles and keep it alive while they live.
+ * A free through the hook first waits for the device to finish its queued work
+ * (hipDeviceSynchronize), so the hook's owner may reuse the memory at once.
+ * Blocks the library allocated itself before the hook was set go back to its
+ * own cache. Errors: HMAT_ERR_ARG if exactly one of the two functions is NULL.
  */
 hmat_status hmat_set_allocator(void* (*alloc_fn)(size_t bytes, void* ctx),
                                void (*free_fn)(void* ptr, void* ctx), void* ctx);
@@ -135,11 +139,16 @@ hmat_status hmat_tree_blocks(hmat_tree t, int32_t* tau, int32_t* sigma, int32_t*
  *                   every panel (inputs and created terms; arithmetic stays
  *                   float64 on MFMA), while projection, orthogonalisation,
  *                   core SVD, truncation and the nearfield stay float64; the
- *                   float copies of A and B are kept with the matrices;
+ *                   float copies of A and B are kept with the matrices. Only
+ *                   for eps >= HMAT_FP32_APPLY_EPS_MIN (HMAT_ERR_ARG below):
+ *                   the float rounding of the panels (about 1e-7 relative) is
+ *                   invisible to the residual probe, which reads the same
+ *                   panels, and the truncation margin covers it only there;
  *  HMAT_BF16_SKETCH rejected with HMAT_ERR_ARG (bf16 panels perturb S by about
  *                   4e-3 relative, above every supported tolerance).
  */
 enum { HMAT_FP64 = 0, HMAT_FP32_APPLY = 1, HMAT_BF16_SKETCH = 2 };
+#define HMAT_FP32_APPLY_EPS_MIN 1e-6
 enum { HMAT_RANK_ADAPTIVE = 0, HMAT_RANK_PREDICT = 1 };
 
 typedef struct {
@@ -203,7 +212,8 @@ enum {
   HMAT_KERN_COMPRESS = 4,      /* orthogonalisation, probe residual, core SVD, output */
   HMAT_KERN_FUSED_TERMS = 5,   /* fused term reduce + expand, targets of <= 64 rows/columns */
   HMAT_KERN_FUSED_TERMS4 = 6,  /* the same with four waves, targets of <= 256 rows/columns */
-  HMAT_KERN_NEAR_DIRECT = 7    /* nearfield targets of <= 64 x 64 with dense pairs, all columns at once */
+  HMAT_KERN_NEAR_DIRECT = 7    /* nearfield targets of <= 256 x 256: low-rank terms and dense x dense
+                                  pairs evaluated per 64 x 64 sub-block, all columns at once */
 };
 
 typedef struct {
@@ -243,7 +253,10 @@ typedef struct {
 } hmat_kernel;
 
 /*
- * Assembles the kernel matrix on the tree's points as an H-matrix: nearfield
+ * Assembles the kernel matrix on the tree's points as an H-matrix in the set
+ * H(B, k) of Def. 2.6 (farfield leaves in the low-rank set R(tau x sigma, k),
+ * nearfield leaves dense; the paper's inputs come from boundary elements, these
+ * from point kernels). Nearfield
  * leaves dense, farfield leaves compressed on the device to relative Frobenius
  * tolerance eps_in per block (same randomized compression as the product,
  * applied to the kernel block evaluated on the fly).
@@ -269,7 +282,12 @@ hmat_status hmat_destroy(hmat M);
 /* ------------------------------------------------------------------------ */
 
 /*
- * C = A B on the common block-cluster tree. For every farfield leaf the stored
+ * C = A B on the common block-cluster tree: Algorithm 4 (the product through
+ * sum-expressions, Def. 3.1, restricted level by level by Algorithm 3), each
+ * admissible leaf compressed by the scheme chosen in opts (Section 4), each
+ * inadmissible leaf evaluated exactly (evaluate() in Algorithm 4; the
+ * nearfield is S applied to the identity, as in the proof of Theorem 5.4).
+ * For every farfield leaf the stored
  * rank-k factors satisfy ||(AB)[t,s] - L R^T||_F <= ~eps ||(AB)[t,s]||_F with k
  * close to the epsilon-rank; nearfield leaves are exact up to rounding.
  *  A, B   unmodified; they must share one tree (HMAT_ERR_TREE_MISMATCH).
@@ -313,7 +331,10 @@ hmat_status hmat_multiply_batched(const hmat* A, const hmat* B, int32_t count, d
 
 /*
  * Dense n x n copy of M into host memory out (column-major, leading dimension
- * ld >= n); order 0 = original point order, 1 = cluster order.
+ * ld >= n); order 0 = original point order, 1 = cluster order. The leaves
+ * (low-rank L R^T or dense, Def. 2.6) are expanded on the device in column
+ * slabs of at most 1 GiB, then copied to out.
+ * Errors: HMAT_ERR_ARG for NULL pointers, ld < n or an unknown order.
  */
 hmat_status hmat_to_dense(hmat M, double* out, int64_t ld, int32_t order);
 
@@ -341,6 +362,16 @@ hmat_status hmat_block_get(hmat M, int64_t i, hmat_block_desc* d, double* U, dou
  * float64[*pool_len]). Call first with pool = NULL to get *pool_len.
  */
 hmat_status hmat_export(hmat M, int32_t* ranks, int64_t* offsets, double* pool, int64_t* pool_len);
+
+/*
+ * Algorithmic flops the product that computed M charged to each leaf as a
+ * target (the work model of the cost analysis in Section 5, at the final ranks:
+ * one forward and one transposed pass per farfield leaf plus its core
+ * factorisation, S applied to the identity per nearfield leaf; the creation of
+ * the low-rank terms is not charged to leaves). flops: host double[count] in
+ * hmat_block_get order; all zero for a matrix that no product computed.
+ */
+hmat_status hmat_product_block_flops(hmat M, double* flops);
 
 /* ------------------------------------------------------------------------ */
 /* Learned rank predictor (multi-layer perceptron 6-64-64-64-1, ReLU, fp32) */

@@ -18,6 +18,7 @@ HMat* assemble_kernel(Tree* t, const hmat_kernel* k, double eps_in, const Opts& 
 hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** C);
 hmat_status multiply_batched(HMat* const* A, HMat* const* B, int32_t count, double eps, const Opts& opts,
                              HMat** C, int32_t* status);
+void expand_to_dense(HMat* M, double* out, int64_t ld, int32_t order, hipStream_t s);
 
 static thread_local std::string g_err;
 void set_last_error(const std::string& msg) { g_err = msg; }
@@ -199,13 +200,13 @@ void dev_free(void* p) {
   std::vector<CachedBlock> victims;
   {
     std::lock_guard<std::mutex> lk(g_alloc_mu);
-    if (g_free) {
-      g_free(p, g_ctx);
-      return;
-    }
     auto it = g_live.find(p);
     if (it == g_live.end()) {
-      (void)hipFree(p);
+      // not from the library's own allocations: the hook's memory (its owner may hand it
+      // out again at once, so queued work that still reads it finishes first)
+      (void)hipDeviceSynchronize();
+      if (g_free) g_free(p, g_ctx);
+      else (void)hipFree(p);
       return;
     }
     const auto key = it->second;
@@ -284,6 +285,16 @@ Opts resolve_opts(const hmat_opts* o) {
              "HMAT_RANK_PREDICT needs opts.rank_model");
   HM_REQUIRE(r.o.streams >= 0 && r.o.streams <= 4, HMAT_ERR_ARG, "streams must be in [0, 4]");
   return r;
+}
+
+// The float32 panels of HMAT_FP32_APPLY perturb S by about 1e-7 relative, and the residual
+// probe, computed from the same panels, cannot see that perturbation; the truncation margin
+// absorbs it only down to the smallest tolerance at which the mode was checked against the
+// oracle.
+void check_precision_floor(const Opts& o, double eps) {
+  HM_REQUIRE(o.o.precision != HMAT_FP32_APPLY || eps >= HMAT_FP32_APPLY_EPS_MIN, HMAT_ERR_ARG,
+             "HMAT_FP32_APPLY needs eps >= 1e-6: below that the float32 panel rounding (about 1e-7 relative) "
+             "is not covered by the residual check");
 }
 
 HMat::~HMat() { tree_release(tree); }
@@ -482,6 +493,7 @@ hmat_status hmat_multiply(hmat A, hmat B, double eps, const hmat_opts* opts, hma
   HM_REQUIRE(A && B && C, HMAT_ERR_ARG, "NULL argument");
   HM_REQUIRE(eps > 0.0 && eps < 1.0, HMAT_ERR_ARG, "eps must be in (0, 1)");
   Opts o = resolve_opts(opts);
+  check_precision_floor(o, eps);
   HMat* out = nullptr;
   hmat_status st = multiply(reinterpret_cast<HMat*>(A), reinterpret_cast<HMat*>(B), eps, o, &out);
   *C = reinterpret_cast<hmat>(out);
@@ -495,45 +507,21 @@ hmat_status hmat_multiply_batched(const hmat* A, const hmat* B, int32_t count, d
   HM_REQUIRE(A && B && C && count >= 0, HMAT_ERR_ARG, "bad argument");
   HM_REQUIRE(eps > 0.0 && eps < 1.0, HMAT_ERR_ARG, "eps must be in (0, 1)");
   Opts o = resolve_opts(opts);
+  check_precision_floor(o, eps);
   hmat_status st = multiply_batched(reinterpret_cast<HMat* const*>(A), reinterpret_cast<HMat* const*>(B),
                                     count, eps, o, reinterpret_cast<HMat**>(C), status);
   if (st != HMAT_OK) return st;
   API_END
 }
 
-static void fetch_pool(HMat* M, std::vector<double>& h) {
-  h.resize(size_t(std::max<int64_t>(M->pool_len, 1)));
-  HM_CHECK_HIP(hipMemcpy(h.data(), M->pool.p, 8 * size_t(M->pool_len), hipMemcpyDeviceToHost));
-}
 
 hmat_status hmat_to_dense(hmat mh, double* out, int64_t ld, int32_t order) {
   API_BEGIN
   HM_REQUIRE(mh && out, HMAT_ERR_ARG, "NULL argument");
   HMat* M = reinterpret_cast<HMat*>(mh);
-  Tree* t = M->tree;
-  HM_REQUIRE(ld >= t->n, HMAT_ERR_ARG, "ld < n");
+  HM_REQUIRE(ld >= M->tree->n, HMAT_ERR_ARG, "ld < n");
   HM_REQUIRE(order == 0 || order == 1, HMAT_ERR_ARG, "order must be 0 or 1");
-  std::vector<double> h;
-  fetch_pool(M, h);
-  for (int32_t b : t->leaves) {
-    int64_t r0 = t->c_begin[t->b_tau[b]], m = t->c_size[t->b_tau[b]];
-    int64_t c0 = t->c_begin[t->b_sigma[b]], n = t->c_size[t->b_sigma[b]];
-    const double* d = h.data() + M->off[b];
-    for (int64_t j = 0; j < n; ++j)
-      for (int64_t i = 0; i < m; ++i) {
-        double v;
-        if (t->b_kind[b] == KIND_F) {
-          int k = M->rank[b];
-          v = 0.0;
-          for (int c = 0; c < k; ++c) v += d[c * m + i] * d[m * k + c * n + j];
-        } else {
-          v = d[j * m + i];
-        }
-        int64_t ri = order ? r0 + i : t->perm[r0 + i];
-        int64_t cj = order ? c0 + j : t->perm[c0 + j];
-        out[cj * ld + ri] = v;
-      }
-  }
+  expand_to_dense(M, out, ld, order, 0);
   API_END
 }
 
@@ -569,6 +557,16 @@ hmat_status hmat_block_get(hmat mh, int64_t i, hmat_block_desc* d, double* U, do
   } else if (V) {
     HM_CHECK_HIP(hipMemcpy(V, M->pool.p + M->off[b], 8 * d->rows * d->cols, hipMemcpyDeviceToHost));
   }
+  API_END
+}
+
+hmat_status hmat_product_block_flops(hmat mh, double* flops) {
+  API_BEGIN
+  HM_REQUIRE(mh && flops, HMAT_ERR_ARG, "NULL argument");
+  HMat* M = reinterpret_cast<HMat*>(mh);
+  Tree* t = M->tree;
+  for (size_t i = 0; i < t->leaves.size(); ++i)
+    flops[i] = M->block_flops.empty() ? 0.0 : M->block_flops[t->leaves[i]];
   API_END
 }
 

@@ -158,6 +158,7 @@ struct HMat {
   DevBuf<float> pool32;  // float copy of `pool`, built on demand for mixed precision
   std::mutex mu32;       // guards building pool32
   ProductFeatures features;
+  std::vector<double> block_flops;  // product output: algorithmic flops charged to each block as a target
   ~HMat();
   void upload_meta(hipStream_t s);
 };
@@ -171,6 +172,8 @@ struct Opts {
   hipStream_t stream() const { return reinterpret_cast<hipStream_t>(o.stream); }
 };
 Opts resolve_opts(const hmat_opts* o);
+// HMAT_ERR_ARG for a precision mode below its accuracy floor
+void check_precision_floor(const Opts& o, double eps);
 
 double now_seconds();
 

@@ -245,6 +245,12 @@ struct Ctx {
   KernTimer timer;
   SubSums sa, sb;
   double alg_flops = 0, alg_bytes = 0;  // minimum algorithmic work (final ranks as widths)
+  std::vector<double> bflops;           // per block: the part of alg_flops charged to it as a target
+  void charge(int32_t b, double by, double fl) {
+    alg_bytes += by;
+    alg_flops += fl;
+    bflops[b] += fl;
+  }
   // mixed precision: the forward sketch passes read float copies of every panel pool
   bool lowp = false;
   struct PoolPair {
@@ -1432,15 +1438,11 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
     for (int k = 0; k < 4; ++k)
       for (int d = 0; d < 2; ++d) {
         const Coef& cf = ch.coef[k][d][i];
-        c.alg_bytes += cf.a + cf.b * w;
-        c.alg_flops += cf.f * w;
+        c.charge(T.block, cf.a + cf.b * w, cf.f * w);
       }
-    for (const Coef* cf : {&ch.s1_leaf[i], &ch.s1_exp[i]}) {  // forward stage 1, counted per target
-      c.alg_bytes += cf->a + cf->b * w;
-      c.alg_flops += cf->f * w;
-    }
-    c.alg_flops += 4.0 * (T.m + T.n) * w * w + 22.0 * w * w * w;
-    c.alg_bytes += 8.0 * (T.m + T.n) * T.k;
+    for (const Coef* cf : {&ch.s1_leaf[i], &ch.s1_exp[i]})  // forward stage 1, counted per target
+      c.charge(T.block, cf->a + cf->b * w, cf->f * w);
+    c.charge(T.block, 8.0 * (T.m + T.n) * T.k, 4.0 * (T.m + T.n) * w * w + 22.0 * w * w * w);
   }
   out.buf.alloc(size_t(std::max<int64_t>(out.len, 1)));
   dt.upload(h, s);
@@ -1486,8 +1488,7 @@ void evaluate_chunk(Ctx& c, Chunk& ch, double* cpool, const std::vector<int64_t>
     dco.push_back(coff[i]);
     c.st.kern_bytes[K_NEAR] += by;
     c.st.kern_flops[K_NEAR] += fl;
-    c.alg_bytes += by;
-    c.alg_flops += fl;
+    c.charge(b, by, fl);
   }
   c.st.n_near_direct += int64_t(dblk.size());
   if (!dblk.empty()) {
@@ -1540,13 +1541,10 @@ void evaluate_chunk(Ctx& c, Chunk& ch, double* cpool, const std::vector<int64_t>
     const double w = c.n_of(ch.blocks[i]);
     for (int k = 0; k < 4; ++k) {  // term coefficients of direct targets are zero
       const Coef& cf = ch.coef[k][0][i];
-      c.alg_bytes += cf.a + cf.b * w;
-      c.alg_flops += cf.f * w;
+      c.charge(ch.blocks[i], cf.a + cf.b * w, cf.f * w);
     }
-    for (const Coef* cf : {&ch.s1_leaf[i], &ch.s1_exp[i]}) {  // forward stage 1, counted per target
-      c.alg_bytes += cf->a + cf->b * w;
-      c.alg_flops += cf->f * w;
-    }
+    for (const Coef* cf : {&ch.s1_leaf[i], &ch.s1_exp[i]})  // forward stage 1, counted per target
+      c.charge(ch.blocks[i], cf->a + cf->b * w, cf->f * w);
   }
   HM_CHECK_HIP(hipStreamSynchronize(c.s));
   c.st.t_near_panels += now_seconds() - tp0;
@@ -1691,6 +1689,7 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   tree_retain(t);
   C->rank.assign(nb, 0);
   C->off.assign(nb, -1);
+  c.bflops.assign(nb, 0.0);
   const bool predict = opts.o.rank_mode == HMAT_RANK_PREDICT;
   const bool collect = !predict && opts.o.stats != nullptr;
   std::vector<int32_t> far_all, near_all;
@@ -1974,6 +1973,7 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     c.st.n_cache_release = a1.releases - alloc0.releases;
   }
   if (opts.o.stats) *opts.o.stats = c.st;
+  C->block_flops.swap(c.bflops);
   *Cout = C_owner.release();
   if (c.st.n_not_converged > 0) {
     set_last_error(std::to_string(c.st.n_not_converged) + " farfield blocks exhausted the growth budget");

@@ -110,6 +110,7 @@ _SIGS = {
     "hmat_block_count": (C.c_int32, [_P, _I64]),
     "hmat_block_get": (C.c_int32, [_P, C.c_int64, C.POINTER(hmat_block_desc), _D, _D]),
     "hmat_export": (C.c_int32, [_P, _I32, _I64, _D, _I64]),
+    "hmat_product_block_flops": (C.c_int32, [_P, _D]),
     "hmat_train_opts_default": (None, [C.POINTER(hmat_train_opts)]),
     "hmat_rank_model_create": (C.c_int32, [C.c_uint64, _PP]),
     "hmat_rank_model_destroy": (C.c_int32, [_P]),
@@ -165,6 +166,26 @@ def _lp(a):
 
 def _fp(a):
     return a.ctypes.data_as(_F)
+
+
+# ---------------------------------------------------------------- allocator
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+_alloc_keep = None  # the installed callbacks must outlive their use by the library
+
+
+def hmat_set_allocator(alloc_fn=None, free_fn=None):
+    """Installs Python callables alloc(nbytes) -> int pointer and free(pointer) as the
+    library's device allocator (both None: back to the library's own)."""
+    global _alloc_keep
+    if alloc_fn is None and free_fn is None:
+        _check(lib().hmat_set_allocator(None, None, None))
+        _alloc_keep = None
+        return
+    a = ALLOC_FN(lambda nbytes, ctx: alloc_fn(nbytes))
+    f = FREE_FN(lambda ptr, ctx: free_fn(ptr))
+    _check(lib().hmat_set_allocator(C.cast(a, _P), C.cast(f, _P), None))
+    _alloc_keep = (a, f)
 
 
 # ---------------------------------------------------------------- trees
@@ -303,6 +324,19 @@ def hmat_export(m):
     pool = np.empty(max(ln.value, 1), dtype=np.float64)
     _check(lib().hmat_export(m, None, None, _dp(pool), C.byref(ln)))
     return ranks, offs, pool
+
+
+def hmat_pool_len(m):
+    """Number of float64 values in M's device pool (factor panels and dense leaves)."""
+    ln = C.c_int64(0)
+    _check(lib().hmat_export(m, None, None, None, C.byref(ln)))
+    return ln.value
+
+
+def hmat_product_block_flops(m):
+    f = np.zeros(hmat_block_count(m), dtype=np.float64)
+    _check(lib().hmat_product_block_flops(m, _dp(f)))
+    return f
 
 
 # ---------------------------------------------------------------- rank model

@@ -103,3 +103,31 @@ def test_batched_reports_per_product_errors(H, products):
 def test_batched_empty(H):
     Cs, status = H.hmat_multiply_batched([], [], 1e-6, H.hmat_opts_default())
     assert Cs == [] and list(status) == []
+
+
+BATCH64_SKIP = ("batch of 64 products (4096 to 65536 points): a second call on this batch stopped making "
+                "progress on the GPU, and the cause is not shown; the case stays off the GPU until it is")
+
+
+@pytest.mark.skip(reason=BATCH64_SKIP)
+def test_batched64_two_calls(H):
+    """The 64-product workload (n log-uniform in [4096, 65536], random geometries and
+    kernel pairs), called twice: both calls complete, and every product of the
+    second call equals the first (plain mode is deterministic)."""
+    from workloads import batched_geometries
+    specs = batched_geometries(64, seed=0)
+    trees, As, Bs = [], [], []
+    for sp in specs:
+        t = H.hmat_build_tree(sp["points"], 64, 0.8, 0)
+        A, _ = H.hmat_assemble(t, sp["kernel_a"], 1.0, 0.0, eps_in=1e-8)
+        B, _ = H.hmat_assemble(t, sp["kernel_b"], 1.0, 0.0, eps_in=1e-8)
+        trees.append(t), As.append(A), Bs.append(B)
+    o = H.hmat_opts_default()
+    C1, s1 = H.hmat_multiply_batched(As, Bs, 1e-6, o)
+    C2, s2 = H.hmat_multiply_batched(As, Bs, 1e-6, o)
+    assert list(s1) == [0] * 64 and list(s2) == [0] * 64
+    for a, b in zip(C1, C2):
+        assert all(np.array_equal(x, y) for x, y in zip(pool_of(H, a), pool_of(H, b)))
+        H.hmat_destroy(a), H.hmat_destroy(b)
+    for t, A, B in zip(trees, As, Bs):
+        H.hmat_destroy(A), H.hmat_destroy(B), H.hmat_tree_destroy(t)
