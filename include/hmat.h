@@ -64,18 +64,6 @@ const char* hmat_last_error(void);
 /* Library version string. */
 const char* hmat_version(void);
 
-/*
- * Device allocator hook. When set, every device allocation of the library goes
- * through alloc(bytes, ctx) and free(ptr, ctx) (for instance a framework's
- * caching allocator); when reset with NULL functions, hipMalloc/hipFree are
- * used. Set it before creating handles and keep it alive while they live.
- * A free through the hook first waits for the device to finish its queued work
- * (hipDeviceSynchronize), so the hook's owner may reuse the memory at once.
- * Blocks the library allocated itself before the hook was set go back to its
- * own cache. Errors: HMAT_ERR_ARG if exactly one of the two functions is NULL.
- */
-hmat_status hmat_set_allocator(void* (*alloc_fn)(size_t bytes, void* ctx),
-                               void (*free_fn)(void* ptr, void* ctx), void* ctx);
 
 /* ------------------------------------------------------------------------ */
 /* Cluster tree and block-cluster tree (Section 2: Def. 2.2, Def. 2.3,       */

@@ -1,4 +1,4 @@
-// C ABI entry points: handles, error reporting, allocator hook, tree queries,
+// C ABI entry points: handles, error reporting, device allocator, tree queries,
 // assembly, import/export. Every entry point catches everything and reports
 // through hmat_last_error().
 #include <algorithm>
@@ -24,11 +24,8 @@ static thread_local std::string g_err;
 void set_last_error(const std::string& msg) { g_err = msg; }
 
 static std::mutex g_alloc_mu;
-static void* (*g_alloc)(size_t, void*) = nullptr;
-static void (*g_free)(void*, void*) = nullptr;
-static void* g_ctx = nullptr;
 
-// Caching of device blocks when no allocator hook is set: a freed block keeps
+// Caching of device blocks: a freed block keeps
 // its (rounded) size class, the stream current at the free and an event
 // recorded there. It is handed out again to work on the same stream at once
 // (stream order puts the new use after the old one), to other streams only once
@@ -141,11 +138,6 @@ void* dev_alloc(size_t bytes) {
   const size_t rs = round_size(bytes);
   {
     std::lock_guard<std::mutex> lk(g_alloc_mu);
-    if (g_alloc) {
-      p = g_alloc(bytes, g_ctx);
-      if (!p) throw Error(HMAT_ERR_OOM, "allocator hook failed for " + std::to_string(bytes) + " bytes");
-      return p;
-    }
     // best fit: the smallest cached size class of at least rs and at most 1.5 rs whose
     // last use has completed
     for (auto it = g_cache.lower_bound({dev, rs});
@@ -202,11 +194,7 @@ void dev_free(void* p) {
     std::lock_guard<std::mutex> lk(g_alloc_mu);
     auto it = g_live.find(p);
     if (it == g_live.end()) {
-      // not from the library's own allocations: the hook's memory (its owner may hand it
-      // out again at once, so queued work that still reads it finishes first)
-      (void)hipDeviceSynchronize();
-      if (g_free) g_free(p, g_ctx);
-      else (void)hipFree(p);
+      (void)hipFree(p);
       return;
     }
     const auto key = it->second;
@@ -336,17 +324,6 @@ extern "C" {
 
 const char* hmat_last_error(void) { return g_err.c_str(); }
 const char* hmat_version(void) { return "hmat-mi355x 0.1"; }
-
-hmat_status hmat_set_allocator(void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, void*), void* ctx) {
-  API_BEGIN
-  HM_REQUIRE((alloc_fn == nullptr) == (free_fn == nullptr), HMAT_ERR_ARG,
-             "alloc and free must be both set or both NULL");
-  std::lock_guard<std::mutex> lk(g_alloc_mu);
-  g_alloc = alloc_fn;
-  g_free = free_fn;
-  g_ctx = ctx;
-  API_END
-}
 
 void hmat_opts_default(hmat_opts* o) {
   if (!o) return;

@@ -93,7 +93,6 @@ _I64 = C.POINTER(C.c_int64)
 _SIGS = {
     "hmat_last_error": (C.c_char_p, []),
     "hmat_version": (C.c_char_p, []),
-    "hmat_set_allocator": (C.c_int32, [_P, _P, _P]),
     "hmat_build_tree": (C.c_int32, [_D, C.c_int64, C.c_int32, C.c_double, C.c_int32, _PP]),
     "hmat_tree_destroy": (C.c_int32, [_P]),
     "hmat_tree_info": (C.c_int32, [_P, C.POINTER(hmat_tree_info_t)]),
@@ -166,26 +165,6 @@ def _lp(a):
 
 def _fp(a):
     return a.ctypes.data_as(_F)
-
-
-# ---------------------------------------------------------------- allocator
-ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
-FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
-_alloc_keep = None  # the installed callbacks must outlive their use by the library
-
-
-def hmat_set_allocator(alloc_fn=None, free_fn=None):
-    """Installs Python callables alloc(nbytes) -> int pointer and free(pointer) as the
-    library's device allocator (both None: back to the library's own)."""
-    global _alloc_keep
-    if alloc_fn is None and free_fn is None:
-        _check(lib().hmat_set_allocator(None, None, None))
-        _alloc_keep = None
-        return
-    a = ALLOC_FN(lambda nbytes, ctx: alloc_fn(nbytes))
-    f = FREE_FN(lambda ptr, ctx: free_fn(ptr))
-    _check(lib().hmat_set_allocator(C.cast(a, _P), C.cast(f, _P), None))
-    _alloc_keep = (a, f)
 
 
 # ---------------------------------------------------------------- trees

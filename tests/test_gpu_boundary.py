@@ -2,8 +2,6 @@
 
 * hmat_to_dense in both point orders against the oracle's densification of the
   library's exported leaves;
-* hmat_set_allocator with PyTorch's caching allocator plugged in: the product is
-  bit-identical to the one with the library's own allocator;
 * HMAT_FP32_APPLY rejected below its accuracy floor;
 * special cases of the product with a plain answer: A = B symmetric (mirrored
   blocks have equal epsilon-ranks, so the library's ranks agree within the rank
@@ -63,42 +61,6 @@ def test_to_dense_both_orders(H):
     assert HM.lib().hmat_to_dense(A, out.ctypes.data_as(HM._D), n, 2) == H.HMAT_ERR_ARG
     for h in (A, B, C):
         H.hmat_destroy(h)
-    H.hmat_tree_destroy(t)
-
-
-def test_allocator_hook_with_torch(H):
-    import torch
-    print("[boundary] hmat_set_allocator with torch's caching allocator", flush=True)
-    pts = fibonacci_sphere(2048)
-    t = H.hmat_build_tree(pts, 32, 0.8, 0)
-    A, _ = H.hmat_assemble(t, "laplace_4pi", 1.0, 0.0, eps_in=1e-8)
-    C0, _ = H.hmat_multiply(A, A, 1e-6)
-    ref = _export_all(H, t, C0)
-    H.hmat_destroy(C0)
-    calls = {"alloc": 0, "free": 0}
-
-    def alloc(nbytes):
-        calls["alloc"] += 1
-        return torch.cuda.caching_allocator_alloc(int(nbytes))
-
-    def free(ptr):
-        calls["free"] += 1
-        torch.cuda.caching_allocator_delete(ptr)
-
-    H.hmat_set_allocator(alloc, free)
-    try:
-        A2, _ = H.hmat_assemble(t, "laplace_4pi", 1.0, 0.0, eps_in=1e-8)
-        C1, _ = H.hmat_multiply(A2, A2, 1e-6)
-        got = _export_all(H, t, C1)
-        H.hmat_destroy(C1)
-        H.hmat_destroy(A2)
-    finally:
-        H.hmat_set_allocator(None, None)
-    print(f"  hook calls: {calls}", flush=True)
-    assert calls["alloc"] > 0 and calls["free"] == calls["alloc"]
-    for a, b in zip(ref, got):
-        assert np.array_equal(a, b)
-    H.hmat_destroy(A)
     H.hmat_tree_destroy(t)
 
 
