@@ -189,6 +189,13 @@ typedef struct {
   /* size of the symbolic plan: low-rank terms created, pairs kept at leaves */
   int64_t n_terms;
   int64_t n_leaf_pairs;
+  /* farfield blocks: iterations of ACA / Lanczos kept (summed), columns of the
+   * fixed-rank sketch, blocks truncated exactly by Algorithm 5, and final SVDs whose
+   * Jacobi iteration reached its sweep cap (their factors are still exact, their
+   * truncation may keep more columns than needed) */
+  int64_t scheme_steps;
+  int64_t n_exact_lowrank;
+  int64_t n_svd_sweep_cap;
 } hmat_stats;
 
 /* Kernel families of hmat_stats.kern_* */
@@ -221,8 +228,35 @@ typedef struct {
   int64_t workspace_limit;     /* bytes of device workspace per subtree batch (0 = auto) */
   int32_t streams;     /* hmat_multiply_batched: products in flight at once, each on its own
                           stream and host thread, 1..4 (0 = autotuned, default) */
-  int32_t pad;
+  int32_t scheme;      /* low-rank scheme of the farfield targets, HMAT_SCHEME_* (default
+                          HMAT_SCHEME_RANDOMIZED) */
+  int32_t k_fixed;     /* 0 (default): eps-adaptive ranks; 1..64: fixed-rank mode (Section 4,
+                          fixed rank approximation): ACA and Lanczos stop after k_fixed steps,
+                          the randomized scheme runs Algorithm 9 with k_fixed columns; eps is
+                          then not used for the farfield blocks */
+  int32_t subspace_iters; /* q of Algorithm 9 (fixed-rank randomized scheme), 0..8 (default 1) */
+  int32_t exact_lowrank;  /* 1: farfield targets whose sum-expression has no H-pairs left
+                             (S_H empty) are truncated exactly by the SVD of their low-rank sum
+                             (Algorithm 5) when it fits the 64-column panels; 0 (default): every
+                             target uses `scheme` */
+  int32_t pad2;
 } hmat_opts;
+
+/* Low-rank schemes of Section 4 (hmat_opts.scheme). Every scheme touches a target's
+ * sum-expression only through products S X and S^T X:
+ *  HMAT_SCHEME_RANDOMIZED  blocked randomized range finder with the a-posteriori
+ *                          residual check and adaptive growth (Algorithm 8 in blocked form),
+ *                          or Algorithm 9 in fixed-rank mode;
+ *  HMAT_SCHEME_ACA         adaptive cross approximation with partial pivoting
+ *                          (Algorithm 6), stopping rule eq. (truncaca), recompressed by
+ *                          Algorithm 5 to the eps-rank;
+ *  HMAT_SCHEME_LANCZOS     Golub-Kahan-Lanczos bidiagonalization with reorthogonalization
+ *                          (Algorithm 7), same stopping rule, SVD of the bidiagonal.
+ * ACA and Lanczos take one matrix-vector product with S and one with S^T per step and
+ * stop after at most 64 steps (HMAT_ERR_NOT_CONVERGED if a block needs more). Their
+ * start values: ACA starts at the block's first row; Lanczos starts from column 0 of the
+ * product's Gaussian matrix (opts.seed). */
+enum { HMAT_SCHEME_RANDOMIZED = 0, HMAT_SCHEME_ACA = 1, HMAT_SCHEME_LANCZOS = 2 };
 
 /* Fills *o with the defaults listed above. */
 void hmat_opts_default(hmat_opts* o);
@@ -312,6 +346,48 @@ hmat_status hmat_multiply(hmat A, hmat B, double eps, const hmat_opts* opts, hma
  */
 hmat_status hmat_multiply_batched(const hmat* A, const hmat* B, int32_t count, double eps,
                                   const hmat_opts* opts, hmat* C, int32_t* status);
+
+/* ------------------------------------------------------------------------ */
+/* H-matrix times vectors                                                   */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * y = M x (trans = 0) or y = M^T x (trans = 1) for a block of nvec vectors:
+ * Algorithm 2 (HtimesV) run over the leaves of the block-cluster tree; every
+ * farfield leaf contributes L (R^T x[sigma]), every nearfield leaf D x[sigma].
+ * x and y are DEVICE memory, column-major n x nvec with leading dimensions
+ * ldx, ldy >= n, rows in original point order (order = 0) or cluster order
+ * (order = 1); y is overwritten and must not overlap x. The work is enqueued on
+ * `stream` (hipStream_t, NULL = null stream) and the call returns without
+ * waiting; y is complete when the stream passes this point. Each output entry
+ * is summed by one thread in a fixed order, so results are deterministic.
+ * Device scratch (one int64 per block plus nvec doubles per farfield rank
+ * unit) comes from the library's allocator and is reused once the stream has
+ * passed the call.
+ * Errors: HMAT_ERR_ARG for NULL pointers, trans/order outside {0, 1},
+ * nvec < 1, ldx or ldy < n, overlapping x and y, or a current device other
+ * than the one M lives on.
+ */
+hmat_status hmat_matvec(hmat M, int32_t trans, int32_t order, int32_t nvec, const double* x, int64_t ldx,
+                        double* y, int64_t ldy, void* stream);
+
+/*
+ * Accuracy estimate of a product C ~ A B (the error estimator of the paper's
+ * numerical examples): subspace iteration on E v = C v - A (B v), whose
+ * products are three calls of Algorithm 2. From the start block X0 (DEVICE
+ * memory, n x p column-major, cluster order, p in [1, n]; the caller draws it,
+ * for instance Gaussian): repeat iters times Y = orth(E X), X = orth(E^T Y);
+ * *err = ||E X||_F. *norm_ab is the same estimate for v -> A (B v) from the same
+ * X0, so *err / *norm_ab estimates the relative error ||C - A B||_F / ||A B||_F
+ * on the dominant p-dimensional subspaces. Runs on `stream` and returns when
+ * both values are on the host. Device scratch: 4 n p doubles plus one matvec
+ * scratch, from the library's allocator.
+ * Errors: HMAT_ERR_ARG for NULL pointers, p outside [1, n], iters outside
+ * [0, 100] or a current device other than the matrices'; HMAT_ERR_TREE_MISMATCH
+ * unless C, A and B share one tree.
+ */
+hmat_status hmat_error_estimate(hmat C, hmat A, hmat B, const double* X0, int32_t p, int32_t iters, void* stream,
+                                double* err, double* norm_ab);
 
 /* ------------------------------------------------------------------------ */
 /* Export                                                                   */

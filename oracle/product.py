@@ -144,6 +144,30 @@ def global_error_estimate(C: HMatrix, A: HMatrix, B: HMatrix, iters: int = 10, s
     return est_err, est_norm
 
 
+def subspace_frobenius(op, opT, X0, iters):
+    """Frobenius-norm estimate of an operator E given through op(X) = E X and
+    opT(Y) = E^T Y: subspace iteration from the start block X0 (n x p),
+    Y = orth(E X), X = orth(E^T Y), repeated `iters` times, then ||E X||_F. With
+    orthonormal X this is the norm of E on the p-dimensional subspace that the
+    iteration converges to (its dominant right singular subspace), the
+    estimator of the numerical-examples section. Orthonormalization is a thin QR."""
+    X = np.linalg.qr(np.asarray(X0, dtype=np.float64))[0]
+    for _ in range(iters):
+        Y = np.linalg.qr(op(X))[0]
+        X = np.linalg.qr(opT(Y))[0]
+    return float(np.linalg.norm(op(X)))
+
+
+def product_error_estimate(C: HMatrix, A: HMatrix, B: HMatrix, X0, iters: int):
+    """(estimate of ||C - A B||_F, estimate of ||A B||_F) by subspace_frobenius
+    on v -> C v - A (B v) and on v -> A (B v), both from the start block X0
+    (cluster order)."""
+    err = subspace_frobenius(lambda X: C.matvec(X) - A.matvec(B.matvec(X)),
+                             lambda Y: C.rmatvec(Y) - B.rmatvec(A.rmatvec(Y)), X0, iters)
+    nrm = subspace_frobenius(lambda X: A.matvec(B.matvec(X)), lambda Y: B.rmatvec(A.rmatvec(Y)), X0, iters)
+    return err, nrm
+
+
 class LeafStrips:
     """Strip densification from an arbitrary source of leaves: arrays of the
     leaves' row/column ranges and a callable returning a leaf's dense block.

@@ -26,7 +26,7 @@ COMMON = [
 # per-source extra flags: the tree builder must not fuse multiply-adds
 EXTRA = {"tree.cpp": ["-ffp-contract=off"]}
 
-SOURCES = ["api.cpp", "tree.cpp", "multiply.cpp", "compress.hip", "assemble.hip", "product.hip", "mlp.hip", "export.hip"]
+SOURCES = ["api.cpp", "tree.cpp", "multiply.cpp", "compress.hip", "assemble.hip", "product.hip", "mlp.hip", "export.hip", "schemes.hip", "matvec.hip", "estimate.hip"]
 
 
 def hipcc():

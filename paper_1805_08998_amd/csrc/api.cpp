@@ -10,6 +10,7 @@
 #include <unordered_map>
 
 #include "hmat_internal.h"
+#include "matvec.h"
 
 namespace hm {
 
@@ -272,6 +273,16 @@ Opts resolve_opts(const hmat_opts* o) {
   HM_REQUIRE(r.o.rank_mode != HMAT_RANK_PREDICT || r.o.rank_model != nullptr, HMAT_ERR_ARG,
              "HMAT_RANK_PREDICT needs opts.rank_model");
   HM_REQUIRE(r.o.streams >= 0 && r.o.streams <= 4, HMAT_ERR_ARG, "streams must be in [0, 4]");
+  HM_REQUIRE(r.o.scheme >= HMAT_SCHEME_RANDOMIZED && r.o.scheme <= HMAT_SCHEME_LANCZOS, HMAT_ERR_ARG,
+             "unknown scheme");
+  HM_REQUIRE(r.o.k_fixed >= 0 && r.o.k_fixed <= 64, HMAT_ERR_ARG, "k_fixed must be in [0, 64]");
+  HM_REQUIRE(r.o.subspace_iters >= 0 && r.o.subspace_iters <= 8, HMAT_ERR_ARG, "subspace_iters must be in [0, 8]");
+  HM_REQUIRE(r.o.exact_lowrank == 0 || r.o.exact_lowrank == 1, HMAT_ERR_ARG, "exact_lowrank must be 0 or 1");
+  const bool plain_randomized = r.o.scheme == HMAT_SCHEME_RANDOMIZED && r.o.k_fixed == 0;
+  HM_REQUIRE(r.o.rank_mode != HMAT_RANK_PREDICT || plain_randomized, HMAT_ERR_ARG,
+             "HMAT_RANK_PREDICT sizes the first sketch of the adaptive randomized scheme only");
+  HM_REQUIRE(r.o.precision != HMAT_FP32_APPLY || plain_randomized, HMAT_ERR_ARG,
+             "HMAT_FP32_APPLY applies to the sketch passes of the adaptive randomized scheme only");
   return r;
 }
 
@@ -293,6 +304,27 @@ void HMat::upload_meta(hipStream_t s) {
 }
 
 void hmat_release(HMat* m) { delete m; }
+
+// Checks shared by the matvec entry points; returns M.
+HMat* check_matvec_args(hmat mh, int32_t trans, int32_t order, int32_t nvec, const double* x, int64_t ldx,
+                        const double* y, int64_t ldy) {
+  HM_REQUIRE(mh && x && y, HMAT_ERR_ARG, "NULL argument");
+  HMat* M = reinterpret_cast<HMat*>(mh);
+  const int64_t n = M->tree->n;
+  HM_REQUIRE(trans == 0 || trans == 1, HMAT_ERR_ARG, "trans must be 0 or 1");
+  HM_REQUIRE(order == 0 || order == 1, HMAT_ERR_ARG, "order must be 0 or 1");
+  HM_REQUIRE(nvec >= 1, HMAT_ERR_ARG, "nvec must be >= 1");
+  HM_REQUIRE(ldx >= n && ldy >= n, HMAT_ERR_ARG, "ldx and ldy must be >= n");
+  const char* xb = reinterpret_cast<const char*>(x);
+  const char* yb = reinterpret_cast<const char*>(y);
+  const int64_t xl = 8 * (ldx * (nvec - 1) + n), yl = 8 * (ldy * (nvec - 1) + n);
+  HM_REQUIRE(xb + xl <= yb || yb + yl <= xb, HMAT_ERR_ARG, "x and y overlap");
+  int dev = 0;
+  HM_CHECK_HIP(hipGetDevice(&dev));
+  HM_REQUIRE(M->tree->dev != nullptr && M->tree->dev_id == dev, HMAT_ERR_ARG,
+             "the current device is not the one the H-matrix lives on");
+  return M;
+}
 
 }  // namespace hm
 
@@ -337,6 +369,8 @@ void hmat_opts_default(hmat_opts* o) {
   o->p_l = 2;
   o->delta = 0.2;
   o->seed = 0x5eedull;
+  o->scheme = HMAT_SCHEME_RANDOMIZED;
+  o->subspace_iters = 1;
 }
 
 hmat_status hmat_build_tree(const double* xyz, int64_t n, int32_t leaf_size, double eta, int32_t split,
@@ -491,6 +525,35 @@ hmat_status hmat_multiply_batched(const hmat* A, const hmat* B, int32_t count, d
   API_END
 }
 
+
+hmat_status hmat_matvec(hmat mh, int32_t trans, int32_t order, int32_t nvec, const double* x, int64_t ldx,
+                        double* y, int64_t ldy, void* stream) {
+  API_BEGIN
+  HMat* M = check_matvec_args(mh, trans, order, nvec, x, ldx, y, ldy);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  set_current_stream(s);
+  DevBuf<double> scratch(size_t(matvec_scratch_doubles(M, nvec)));
+  matvec_launch(M, trans, order, nvec, x, ldx, y, ldy, scratch.p, s);
+  API_END
+}
+
+hmat_status hmat_error_estimate(hmat Ch, hmat Ah, hmat Bh, const double* X0, int32_t p, int32_t iters, void* stream,
+                                double* err, double* norm_ab) {
+  API_BEGIN
+  HM_REQUIRE(Ch && Ah && Bh && X0 && err && norm_ab, HMAT_ERR_ARG, "NULL argument");
+  HMat* C = reinterpret_cast<HMat*>(Ch);
+  HMat* A = reinterpret_cast<HMat*>(Ah);
+  HMat* B = reinterpret_cast<HMat*>(Bh);
+  HM_REQUIRE(A->tree == B->tree && C->tree == A->tree, HMAT_ERR_TREE_MISMATCH, "C, A and B must share one tree");
+  HM_REQUIRE(p >= 1 && p <= A->tree->n, HMAT_ERR_ARG, "p must be in [1, n]");
+  HM_REQUIRE(iters >= 0 && iters <= 100, HMAT_ERR_ARG, "iters must be in [0, 100]");
+  int dev = 0;
+  HM_CHECK_HIP(hipGetDevice(&dev));
+  HM_REQUIRE(A->tree->dev != nullptr && A->tree->dev_id == dev, HMAT_ERR_ARG,
+             "the current device is not the one the H-matrices live on");
+  error_estimate(C, A, B, X0, p, iters, reinterpret_cast<hipStream_t>(stream), err, norm_ab);
+  API_END
+}
 
 hmat_status hmat_to_dense(hmat mh, double* out, int64_t ld, int32_t order) {
   API_BEGIN

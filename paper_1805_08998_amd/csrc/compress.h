@@ -17,6 +17,7 @@
 #pragma once
 
 #include "hmat_internal.h"
+#include "product_kernels.h"
 
 namespace hm {
 
@@ -37,6 +38,8 @@ struct CTarget {
   int32_t block;       // block id
   int32_t w0;          // initial sketch width of this target (b0 or predicted)
 };
+
+constexpr int CAPMAX_CORE = 64;  // largest column count of the per-target panels and cores
 
 struct CParams {
   int32_t cap;     // column capacity of Q / Z
@@ -60,6 +63,11 @@ void launch_check(CTarget* t, int nt, const CParams& p, int32_t* n_pending, hipS
 // QR of Z, Jacobi SVD of the core, truncation: sets k and keeps W, J, sigma in core.
 // rmax: the largest rz among the targets (0: use the capacity)
 void launch_core(CTarget* t, int nt, const CParams& p, hipStream_t s, int rmax = 0);
+// Algorithm 5 (SVD of a low-rank sum): columns [c0, c0 + cnt) of the target's stacked
+// term factor [L_1 core_1, L_2 core_2, ...] (restricted to tau, terms of the block and
+// of its ancestors in creation order) into Y[:, cap .. cap + cnt); zero past the last
+// term column.
+void launch_term_columns(CTarget* t, int nt, const TreeView& tv, int c0, int cnt, int cap, hipStream_t s);
 // L = Q W[:, :k] and R = Qz J[:, :k] into pool + out_off.
 void launch_write_factors(CTarget* t, int nt, const CParams& p, double* pool, hipStream_t s);
 

@@ -269,6 +269,57 @@ void launch_core(CTarget* t, int nt, const CParams& p, hipStream_t s, int rmax) 
   HM_CHECK_HIP(hipGetLastError());
 }
 
+// ---------------------------------------------------------------- stacked term columns
+__global__ void __launch_bounds__(NT) k_term_columns(CTarget* __restrict__ tg, TreeView tv, int c0, int cnt, int cap) {
+  __shared__ int sel_term, sel_col;
+  CTarget& T = tg[blockIdx.x];
+  const int m = T.m;
+  for (int j = 0; j < cnt; ++j) {
+    double* dst = T.Y + int64_t(cap + j) * m;
+    if (threadIdx.x == 0) {
+      // find the term holding stacked column c0 + j: terms of the block, then of its ancestors
+      int gc = c0 + j, term = -1, col = 0;
+      for (int a = T.block; a >= 0 && term < 0; a = tv.b_parent[a])
+        for (int it = tv.group_ptr[a]; it < tv.group_ptr[a + 1]; ++it) {
+          const int kr = tv.terms[it].kr;
+          if (gc < kr) {
+            term = it;
+            col = gc;
+            break;
+          }
+          gc -= kr;
+        }
+      sel_term = term;
+      sel_col = col;
+    }
+    __syncthreads();
+    const int it = sel_term, lc = sel_col;
+    if (it < 0) {
+      for (int i = threadIdx.x; i < m; i += NT) dst[i] = 0.0;
+    } else {
+      const Term tm = tv.terms[it];
+      const int64_t r0 = int64_t(T.row0) - tm.lrow0;  // panel row of the target's first row
+      for (int i = threadIdx.x; i < m; i += NT) {
+        double v;
+        if (tm.core) {
+          v = 0.0;
+          for (int c = 0; c < tm.kl; ++c) v += tm.L[r0 + i + int64_t(c) * tm.ldl] * tm.core[c + int64_t(lc) * tm.kl];
+        } else {
+          v = tm.L[r0 + i + int64_t(lc) * tm.ldl];
+        }
+        dst[i] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+void launch_term_columns(CTarget* t, int nt, const TreeView& tv, int c0, int cnt, int cap, hipStream_t s) {
+  if (nt <= 0) return;
+  hipLaunchKernelGGL(k_term_columns, dim3(nt), dim3(NT), 0, s, t, tv, c0, cnt, cap);
+  HM_CHECK_HIP(hipGetLastError());
+}
+
 // ---------------------------------------------------------------- factor output
 __global__ void __launch_bounds__(NT) k_write_factors(const CTarget* __restrict__ tg, int nt, int cap,
                                                       double* __restrict__ pool) {

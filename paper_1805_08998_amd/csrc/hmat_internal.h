@@ -94,6 +94,7 @@ struct DeviceTree {
   DevBuf<int32_t> b_tau, b_sigma, b_kind;
   DevBuf<int32_t> brow_ptr, brow_blk, bcol_ptr, bcol_blk;
   DevBuf<double> xyz_perm;  // points in cluster order, n x 3
+  DevBuf<int32_t> perm;     // cluster position -> original point index
 };
 
 struct Tree {

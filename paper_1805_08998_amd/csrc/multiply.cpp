@@ -24,6 +24,7 @@
 
 #include "compress.h"
 #include "product_kernels.h"
+#include "schemes.h"
 
 namespace hm {
 
@@ -862,6 +863,11 @@ struct Chunk {
   // nearfield chunks: targets of at most NEAR_MAX rows and columns are evaluated by the
   // direct kernel (terms and dense x dense pairs); their other pairs stay in `pairs`
   bool near = false;
+  // Forward stage-1 sharing holds when every target's input is fixed by sigma (rows of
+  // Omega, identity columns). The ACA, Lanczos and fixed-rank schemes apply S to inputs of
+  // their own (unit vectors at per-target pivots, Lanczos vectors, power-iteration bases):
+  // their chunks give every pair its own stage-1 task.
+  bool share_s1 = true;
   std::vector<uint8_t> direct;
   std::vector<int32_t> dpptr, dpairs;  // per direct target (chunk order): dense pairs (A block, B block)
   // Forward stage 1 of a pair, B[rho, sigma] X, depends only on the pair block and on X, and
@@ -910,6 +916,7 @@ struct Chunk {
     is_small.clear();
     feats.clear();
     near = false;
+    share_s1 = true;
     direct.clear();
     dpptr.clear();
     dpairs.clear();
@@ -987,7 +994,8 @@ void build_chunk(const Ctx& c, Chunk& ch, bool features) {
   ch.s1_exp.assign(nt, Coef{});
   ch.g_leaf.clear();
   ch.g_exp.clear();
-  std::unordered_map<int32_t, int32_t> group_of;  // pair block B[rho, sigma] -> stage-1 group
+  // pair block B[rho, sigma] (and, without sharing, the target) -> stage-1 group
+  std::unordered_map<int64_t, int32_t> group_of;
   std::vector<int64_t> group_off;                 // its temporary
   std::vector<std::pair<int32_t, int32_t>> members;
   for (int i = 0; i < nt; ++i) {
@@ -1076,10 +1084,11 @@ void build_chunk(const Ctx& c, Chunk& ch, bool features) {
         L.add(c, tk, true);
       };
       // forward: B[rho, sigma] X -> temp1 of the pair block's group, then A[tau, rho] temp1 -> temp2
-      auto gi = group_of.find(qb);
+      const int64_t gkey = ch.share_s1 ? int64_t(qb) : (int64_t(i) << 32) | int64_t(uint32_t(qb));
+      auto gi = group_of.find(gkey);
       if (gi == group_of.end()) {
         const int32_t g = int32_t(group_off.size());
-        gi = group_of.emplace(qb, g).first;
+        gi = group_of.emplace(gkey, g).first;
         group_off.push_back(ch.pair_len);
         ch.pair_len += int64_t(t.c_size[rho]) * PW;
         ch.g_leaf.emplace_back();
@@ -1215,6 +1224,29 @@ struct FarOut {
   int64_t len = 0;
 };
 
+// Minimum algorithmic work of farfield target i of a chunk at final rank k: one forward
+// and one transposed pass of width k, the core factorisations and the factor output.
+void charge_far(Ctx& c, const Chunk& ch, int i, int32_t block, int m, int n, int k) {
+  const double w = std::max(k, 1);
+  for (int kk = 0; kk < 4; ++kk)
+    for (int d = 0; d < 2; ++d) {
+      const Coef& cf = ch.coef[kk][d][i];
+      c.charge(block, cf.a + cf.b * w, cf.f * w);
+    }
+  for (const Coef* cf : {&ch.s1_leaf[i], &ch.s1_exp[i]})  // forward stage 1, counted per target
+    c.charge(block, cf->a + cf->b * w, cf->f * w);
+  c.charge(block, 8.0 * (m + n) * k, 4.0 * (m + n) * w * w + 22.0 * w * w * w);
+}
+
+// Omega with at least ncol columns (rows keyed by position, so regenerating it for more
+// columns keeps the existing ones).
+void ensure_omega(Ctx& c, int64_t ncol) {
+  if (c.omega_cols >= ncol) return;
+  c.omega.alloc(size_t(c.t->n) * size_t(ncol));
+  launch_fill_gaussian(c.omega.p, c.t->n, int32_t(ncol), c.opts.o.seed, c.s);
+  c.omega_cols = ncol;
+}
+
 // Randomized compression of the chunk's farfield targets.
 void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& out) {
   const Tree& t = *c.t;
@@ -1251,11 +1283,7 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
     T.w0 = w0[i];
   }
   // Gaussian columns shared by all targets (rows keyed by position), generated once
-  if (c.omega_cols < ncol_om) {
-    c.omega.alloc(size_t(t.n) * size_t(ncol_om));
-    launch_fill_gaussian(c.omega.p, t.n, int32_t(ncol_om), c.opts.o.seed, s);
-    c.omega_cols = ncol_om;
-  }
+  ensure_omega(c, ncol_om);
   const double* omega_p = c.omega.p;
   DevBuf<CTarget> dt(nt);
   dt.upload(h, s);
@@ -1432,17 +1460,7 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
     T.out_off = out.len;
     out.len += int64_t(T.k) * (T.m + T.n);
     c.st.rank_hist[std::min(T.k, 64)]++;
-    // minimum algorithmic work of this target: one forward and one transposed pass of
-    // width k, the core factorisations and the factor output
-    const double w = std::max(T.k, 1);
-    for (int k = 0; k < 4; ++k)
-      for (int d = 0; d < 2; ++d) {
-        const Coef& cf = ch.coef[k][d][i];
-        c.charge(T.block, cf.a + cf.b * w, cf.f * w);
-      }
-    for (const Coef* cf : {&ch.s1_leaf[i], &ch.s1_exp[i]})  // forward stage 1, counted per target
-      c.charge(T.block, cf->a + cf->b * w, cf->f * w);
-    c.charge(T.block, 8.0 * (T.m + T.n) * T.k, 4.0 * (T.m + T.n) * w * w + 22.0 * w * w * w);
+    charge_far(c, ch, i, T.block, T.m, T.n, T.k);
   }
   out.buf.alloc(size_t(std::max<int64_t>(out.len, 1)));
   dt.upload(h, s);
@@ -1451,6 +1469,400 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
     c.timer.end();
   HM_CHECK_HIP(hipStreamSynchronize(s));
   c.st.t_core += now_seconds() - t3;
+}
+
+// ------------------------------------------------------------------ Algorithm 5
+// Columns of the stacked term factor of a farfield target (sum of the widths of its
+// terms and of its ancestors' terms; every term contributes L core, of kr columns).
+int64_t term_columns(const Ctx& c, int32_t b) {
+  const Tree& t = *c.t;
+  int64_t K = 0;
+  for (int32_t a = b; a >= 0; a = t.b_parent[a])
+    for (int32_t j = c.group_ptr_h[a]; j < c.group_ptr_h[a + 1]; ++j) K += c.sym[j].kr;
+  return K;
+}
+
+// A farfield target is truncated exactly by Algorithm 5 when its sum-expression holds no
+// H-pairs (S_H empty) and its stacked factor spans at most `cap` columns.
+bool exact_eligible(const Ctx& c, int32_t b, int cap) {
+  if (c.hptr[b + 1] != c.hptr[b]) return false;
+  return std::min<int64_t>(c.m_of(b), term_columns(c, b)) <= cap;
+}
+
+// SVD of the low-rank sum S = sum_j L_j core_j R_j^T of targets with S_H empty
+// (Algorithm 5), with the second QR taken of R R_L^T: Q = orth([L_1 core_1, ...]) (the
+// range of S, by CGS2 in batches of PW stacked columns), Z = S^T Q (= R R_L^T up to the
+// basis), QR of Z, SVD of its triangular factor, truncation at eps relative to ||S||_F
+// (no estimated residual: E = 0).
+void compress_chunk_exact(Ctx& c, Chunk& ch, FarOut& out) {
+  const Tree& t = *c.t;
+  hipStream_t s = c.s;
+  const int nt = int(ch.blocks.size());
+  const int cap = CAPMAX_CORE;
+  const CParams cp{cap, PW, c.eps, c.opts.o.delta, 0.0};
+  int64_t need = 0, kmax = 0;
+  std::vector<int64_t> K(nt);
+  for (int i = 0; i < nt; ++i) {
+    const int32_t b = ch.blocks[i];
+    K[i] = term_columns(c, b);
+    kmax = std::max(kmax, K[i]);
+    need += int64_t(c.m_of(b)) * (cap + PW) + int64_t(c.n_of(b)) * cap + 2 * cap * cap + cap;
+  }
+  DevBuf<double> ws{size_t(std::max<int64_t>(need, 1))};
+  std::vector<CTarget> h(nt);
+  int64_t o = 0;
+  for (int i = 0; i < nt; ++i) {
+    const int32_t b = ch.blocks[i];
+    CTarget& T = h[i];
+    std::memset(&T, 0, sizeof(T));
+    T.m = c.m_of(b);
+    T.n = c.n_of(b);
+    T.row0 = t.c_begin[t.b_tau[b]];
+    T.col0 = t.c_begin[t.b_sigma[b]];
+    T.Y = ws.p + o;
+    o += int64_t(T.m) * (cap + PW);
+    T.Z = ws.p + o;
+    o += int64_t(T.n) * cap;
+    T.core = ws.p + o;
+    o += 2 * cap * cap + cap;
+    T.active = 1;
+    T.block = b;
+  }
+  DevBuf<CTarget> dt(nt);
+  dt.upload(h, s);
+  const double t0 = now_seconds();
+  for (int64_t c0 = 0; c0 < kmax; c0 += PW) {
+    c.timer.begin(K_COMPRESS);
+    launch_term_columns(dt.p, nt, c.tv, int(c0), PW, cap, s);
+    launch_orth_append(dt.p, nt, cap, PW, cp, s);
+    c.timer.end();
+  }
+  HM_CHECK_HIP(hipMemcpyAsync(h.data(), dt.p, sizeof(CTarget) * nt, hipMemcpyDeviceToHost, s));
+  HM_CHECK_HIP(hipStreamSynchronize(s));
+  const double t1 = now_seconds();
+  c.st.t_sketch += t1 - t0;
+  // Z = S^T Q
+  int maxw = 0;
+  for (const auto& T : h) maxw = std::max(maxw, T.r);
+  std::vector<TDesc> td(nt);
+  for (int j0 = 0; j0 < maxw; j0 += PW) {
+    bool any = false;
+    for (int i = 0; i < nt; ++i) {
+      TDesc& d = td[i];
+      std::memset(&d, 0, sizeof(d));
+      const CTarget& T = h[i];
+      if (j0 >= T.r) continue;
+      d.w = std::min(PW, T.r - j0);
+      d.trans = 1;
+      d.X = T.Y + int64_t(j0) * T.m;
+      d.ldx = T.m;
+      d.Y = T.Z + int64_t(j0) * T.n;
+      d.ldy = T.n;
+      d.split = d.w;
+      any = true;
+    }
+    if (any) run_pass(c, ch, td, true);
+  }
+  const double t2 = now_seconds();
+  c.st.t_project += t2 - t1;
+  int rmax = 1;
+  for (auto& T : h) {
+    T.rz = T.r;
+    T.E2 = 0.0;
+    T.done = 1;
+    rmax = std::max(rmax, T.rz);
+  }
+  dt.upload(h, s);
+  c.timer.begin(K_COMPRESS);
+  launch_core(dt.p, nt, cp, s, rmax);
+  c.timer.end();
+  HM_CHECK_HIP(hipMemcpyAsync(h.data(), dt.p, sizeof(CTarget) * nt, hipMemcpyDeviceToHost, s));
+  HM_CHECK_HIP(hipStreamSynchronize(s));
+  out.blocks.clear();
+  out.ranks.clear();
+  out.done.clear();
+  out.offs.clear();
+  out.len = 0;
+  for (int i = 0; i < nt; ++i) {
+    CTarget& T = h[i];
+    out.blocks.push_back(T.block);
+    out.ranks.push_back(T.k);
+    out.done.push_back(1);
+    out.offs.push_back(out.len);
+    T.out_off = out.len;
+    out.len += int64_t(T.k) * (T.m + T.n);
+    c.st.rank_hist[std::min(T.k, 64)]++;
+    c.st.n_exact_lowrank++;
+    charge_far(c, ch, i, T.block, T.m, T.n, T.k);
+  }
+  out.buf.alloc(size_t(std::max<int64_t>(out.len, 1)));
+  dt.upload(h, s);
+  c.timer.begin(K_COMPRESS);
+  launch_write_factors(dt.p, nt, cp, out.buf.p, s);
+  c.timer.end();
+  HM_CHECK_HIP(hipStreamSynchronize(s));
+  c.st.t_core += now_seconds() - t2;
+}
+
+// ------------------------------------------------------------------ other schemes
+// Per-target panels of the ACA, Lanczos and fixed-rank schemes.
+struct IterPanels {
+  DevBuf<double> ws;
+  DevBuf<int32_t> used, state;
+  DevBuf<ITarget> dt;
+  std::vector<ITarget> h;
+  std::vector<int32_t> hs;  // per target: state (or column count) read back after a step
+};
+
+void setup_iter(Ctx& c, Chunk& ch, IterPanels& P, int cap, int kfixed) {
+  const Tree& t = *c.t;
+  const int nt = int(ch.blocks.size());
+  int64_t need = 0, needi = 0;
+  for (int32_t b : ch.blocks) {
+    const int64_t m = c.m_of(b), n = c.n_of(b);
+    need += m * cap + n * (cap + 1) + 2 * (m + n) + 2 * int64_t(cap) * cap + 3 * cap;
+    needi += m;
+  }
+  P.ws.alloc(size_t(std::max<int64_t>(need, 1)));
+  P.used.alloc(size_t(std::max<int64_t>(needi, 1)));
+  P.state.alloc(size_t(std::max(nt, 1)));
+  P.h.assign(size_t(nt), ITarget{});
+  P.hs.assign(size_t(nt), 0);
+  int64_t o = 0, oi = 0;
+  for (int i = 0; i < nt; ++i) {
+    const int32_t b = ch.blocks[i];
+    ITarget& T = P.h[i];
+    std::memset(&T, 0, sizeof(T));
+    T.m = c.m_of(b);
+    T.n = c.n_of(b);
+    T.row0 = t.c_begin[t.b_tau[b]];
+    T.col0 = t.c_begin[t.b_sigma[b]];
+    T.L = P.ws.p + o;
+    o += int64_t(T.m) * cap;
+    T.U = P.ws.p + o;
+    o += int64_t(T.n) * (cap + 1);
+    T.xf = P.ws.p + o;
+    o += T.n;
+    T.xt = P.ws.p + o;
+    o += T.m;
+    T.yf = P.ws.p + o;
+    o += T.m;
+    T.yt = P.ws.p + o;
+    o += T.n;
+    T.work = P.ws.p + o;
+    o += 2 * int64_t(cap) * cap + 3 * cap;
+    T.used = P.used.p + oi;
+    oi += T.m;
+    T.block = b;
+    T.lim = std::min({T.m, T.n, cap, kfixed > 0 ? kfixed : cap});
+  }
+  P.dt.upload(P.h, c.s);
+}
+
+void fetch_iter(Ctx& c, IterPanels& P) {
+  const double t0 = now_seconds();
+  HM_CHECK_HIP(hipMemcpyAsync(P.h.data(), P.dt.p, sizeof(ITarget) * P.h.size(), hipMemcpyDeviceToHost, c.s));
+  HM_CHECK_HIP(hipStreamSynchronize(c.s));
+  c.st.t_host[3] += now_seconds() - t0;
+}
+
+void fetch_counts(Ctx& c, IterPanels& P) {
+  const double t0 = now_seconds();
+  HM_CHECK_HIP(hipMemcpyAsync(P.hs.data(), P.state.p, 4 * P.hs.size(), hipMemcpyDeviceToHost, c.s));
+  HM_CHECK_HIP(hipStreamSynchronize(c.s));
+  c.st.t_host[3] += now_seconds() - t0;
+}
+
+// Lays out the outputs of the chunk's targets (rank T.k each) and records them in `out`.
+void layout_outputs(Ctx& c, Chunk& ch, IterPanels& P, FarOut& out) {
+  out.blocks.clear();
+  out.ranks.clear();
+  out.done.clear();
+  out.offs.clear();
+  out.len = 0;
+  for (size_t i = 0; i < P.h.size(); ++i) {
+    ITarget& T = P.h[i];
+    const bool ok = T.state != 2;
+    if (!ok) c.st.n_not_converged++;
+    if (T.svd_sweeps < 0) c.st.n_svd_sweep_cap++;
+    out.blocks.push_back(T.block);
+    out.ranks.push_back(T.k);
+    out.done.push_back(uint8_t(ok ? 1 : 0));
+    out.offs.push_back(out.len);
+    T.out_off = out.len;
+    out.len += int64_t(T.k) * (T.m + T.n);
+    c.st.rank_hist[std::min(T.k, 64)]++;
+    charge_far(c, ch, int(i), T.block, T.m, T.n, T.k);
+  }
+  out.buf.alloc(size_t(std::max<int64_t>(out.len, 1)));
+  P.dt.upload(P.h, c.s);
+}
+
+// ACA (Algorithm 6) or Lanczos bidiagonalization (Algorithm 7) of the chunk's farfield
+// targets: one transposed and one forward pass of width 1 per step for every target
+// still running, the per-target vector work in between, then recompression.
+void compress_chunk_iter(Ctx& c, Chunk& ch, FarOut& out) {
+  const Tree& t = *c.t;
+  hipStream_t s = c.s;
+  const int nt = int(ch.blocks.size());
+  const int cap = ISCHEME_CAP;
+  const int kf = c.opts.o.k_fixed;
+  const IParams ip{cap, kf > 0 ? 1 : 0, c.eps};
+  const bool aca = c.opts.o.scheme == HMAT_SCHEME_ACA;
+  IterPanels P;
+  setup_iter(c, ch, P, cap, kf);
+  const double t0 = now_seconds();
+  for (int i = 0; i < nt; ++i) P.hs[i] = P.h[i].lim == 0 ? 1 : 0;
+  if (aca) {
+    launch_aca_init(P.dt.p, nt, s);
+  } else {
+    ensure_omega(c, 1);
+    launch_gkl_init(P.dt.p, nt, c.omega.p, s);
+  }
+  std::vector<TDesc> td(nt);
+  // one pass of width 1 over the running targets: forward yf = S xf, transposed yt = S^T xt
+  auto vec_pass = [&](bool trans) {
+    bool any = false;
+    for (int i = 0; i < nt; ++i) {
+      TDesc& d = td[i];
+      std::memset(&d, 0, sizeof(d));
+      if (P.hs[i] != 0) continue;
+      const ITarget& T = P.h[i];
+      d.w = 1;
+      d.split = 1;
+      d.trans = trans ? 1 : 0;
+      d.X = trans ? T.xt : T.xf;
+      d.ldx = trans ? T.m : T.n;
+      d.Y = trans ? T.yt : T.yf;
+      d.ldy = trans ? T.n : T.m;
+      any = true;
+    }
+    if (any) run_pass(c, ch, td, trans);
+  };
+  for (int step = 0; step <= cap; ++step) {
+    if (std::none_of(P.hs.begin(), P.hs.end(), [](int32_t v) { return v == 0; })) break;
+    if (aca) {
+      vec_pass(true);  // row e_i^T S of every running target
+      c.timer.begin(K_COMPRESS);
+      launch_aca_row(P.dt.p, nt, ip, s);
+      c.timer.end();
+      vec_pass(false);  // column S e_j
+      c.timer.begin(K_COMPRESS);
+      launch_aca_col(P.dt.p, nt, ip, P.state.p, s);
+      c.timer.end();
+    } else {
+      vec_pass(false);  // S w_r
+      c.timer.begin(K_COMPRESS);
+      launch_gkl_fwd(P.dt.p, nt, ip, s);
+      c.timer.end();
+      vec_pass(true);  // S^T q_r
+      c.timer.begin(K_COMPRESS);
+      launch_gkl_bwd(P.dt.p, nt, ip, P.state.p, s);
+      c.timer.end();
+    }
+    fetch_counts(c, P);
+  }
+  const double t1 = now_seconds();
+  c.st.t_sketch += t1 - t0;
+  c.timer.begin(K_COMPRESS);
+  if (aca) launch_aca_core(P.dt.p, nt, ip, s);
+  else launch_gkl_core(P.dt.p, nt, ip, s);
+  c.timer.end();
+  fetch_iter(c, P);
+  int rmax = 1;
+  for (const auto& T : P.h) {
+    rmax = std::max(rmax, T.r);
+    c.st.scheme_steps += T.r;
+  }
+  c.timer.begin(K_COMPRESS);
+  launch_iter_svd(P.dt.p, nt, ip, rmax, s);
+  c.timer.end();
+  fetch_iter(c, P);
+  for (int i = 0; i < nt; ++i)
+    if (P.h[i].state == 0) P.h[i].state = 2;  // still running after the step cap
+  layout_outputs(c, ch, P, out);
+  c.timer.begin(K_COMPRESS);
+  launch_iter_write(P.dt.p, nt, ip, out.buf.p, s);
+  c.timer.end();
+  HM_CHECK_HIP(hipStreamSynchronize(s));
+  c.st.t_core += now_seconds() - t1;
+  (void)t;
+}
+
+// Fixed-rank randomized scheme (Algorithm 9): L = orth(S Omega_k), q subspace iterations
+// (U = orth(S^T L), L = orth(S U)), output L and R = S^T L.
+void compress_chunk_fixed(Ctx& c, Chunk& ch, FarOut& out) {
+  const Tree& t = *c.t;
+  hipStream_t s = c.s;
+  const int nt = int(ch.blocks.size());
+  const int cap = ISCHEME_CAP;
+  const int k = c.opts.o.k_fixed;
+  IterPanels P;
+  setup_iter(c, ch, P, cap, k);
+  const double t0 = now_seconds();
+  ensure_omega(c, k);
+  std::vector<TDesc> td(nt);
+  std::vector<int32_t> r(nt, k), rz(nt, 0);
+  // passes over per-target column counts cnt[i], PW columns at a time
+  auto passes = [&](bool trans, const std::vector<int32_t>& cnt, bool sketch) {
+    int maxw = 0;
+    for (int v : cnt) maxw = std::max(maxw, v);
+    for (int j0 = 0; j0 < maxw; j0 += PW) {
+      bool any = false;
+      for (int i = 0; i < nt; ++i) {
+        TDesc& d = td[i];
+        std::memset(&d, 0, sizeof(d));
+        if (j0 >= cnt[i]) continue;
+        const ITarget& T = P.h[i];
+        d.w = std::min(PW, cnt[i] - j0);
+        d.split = d.w;
+        d.trans = trans ? 1 : 0;
+        if (sketch) {
+          d.X = c.omega.p + int64_t(j0) * t.n + T.col0;
+          d.ldx = int32_t(t.n);
+        } else {
+          d.X = trans ? T.L + int64_t(j0) * T.m : T.U + int64_t(j0) * T.n;
+          d.ldx = trans ? T.m : T.n;
+        }
+        d.Y = trans ? T.U + int64_t(j0) * T.n : T.L + int64_t(j0) * T.m;
+        d.ldy = trans ? T.n : T.m;
+        any = true;
+      }
+      if (any) run_pass(c, ch, td, trans);
+    }
+  };
+  auto orth = [&](int side, int cnt, std::vector<int32_t>& dst) {
+    c.timer.begin(K_COMPRESS);
+    launch_orth_cols(P.dt.p, nt, side, cnt, P.state.p, s);
+    c.timer.end();
+    fetch_counts(c, P);
+    dst = P.hs;
+  };
+  passes(false, r, true);  // L = S Omega[:, :k]
+  orth(0, k, r);
+  for (int it = 0; it < c.opts.o.subspace_iters; ++it) {
+    passes(true, r, false);  // U = S^T L
+    orth(1, 0, rz);
+    passes(false, rz, false);  // L = S U
+    orth(0, 0, r);
+  }
+  const double t1 = now_seconds();
+  c.st.t_sketch += t1 - t0;
+  passes(true, r, false);  // R = S^T L
+  c.st.t_project += now_seconds() - t1;
+  const double t2 = now_seconds();
+  fetch_iter(c, P);
+  for (auto& T : P.h) {
+    T.k = T.r;
+    T.state = 1;
+    c.st.scheme_steps += k;
+  }
+  layout_outputs(c, ch, P, out);
+  c.timer.begin(K_COMPRESS);
+  launch_copy_out(P.dt.p, nt, out.buf.p, s);
+  c.timer.end();
+  HM_CHECK_HIP(hipStreamSynchronize(s));
+  c.st.t_core += now_seconds() - t2;
 }
 
 // Nearfield targets: S applied to the identity, PW columns at a time, straight into C.
@@ -1712,7 +2124,9 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
                              ? opts.o.workspace_limit
                              : std::min<int64_t>(int64_t(16) << 30,
                                                  int64_t(dev_free_bytes() / (16 * std::max(1, opts.concurrency))));
-  const int cap_est = std::min(64, opts.o.b0 + opts.o.max_growth * opts.o.probes);
+  // ACA, Lanczos and the fixed-rank scheme apply S to per-target vectors
+  const bool own_inputs = opts.o.scheme != HMAT_SCHEME_RANDOMIZED || opts.o.k_fixed > 0;
+  const int cap_est = own_inputs ? ISCHEME_CAP + 4 : std::min(64, opts.o.b0 + opts.o.max_growth * opts.o.probes);
   std::vector<FarOut> outs;
 
   // Targets are processed in chunks; the host work lists of chunk k+1 are built on a
@@ -1755,12 +2169,19 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   struct Job {
     bool far;
     std::vector<int32_t> blocks;
+    bool exact = false;  // farfield targets truncated by Algorithm 5
   };
   auto make_jobs = [&](const std::vector<int32_t>& near, const std::vector<int32_t>& far) {
     std::vector<Job> jobs;
     const double tp = now_seconds();
     for (auto& p : partition(near, false)) jobs.push_back(Job{false, std::move(p)});
-    for (auto& p : partition(far, true)) jobs.push_back(Job{true, std::move(p)});
+    std::vector<int32_t> far_rest, far_exact;
+    if (opts.o.exact_lowrank) {
+      for (int32_t b : far) (exact_eligible(c, b, CAPMAX_CORE) ? far_exact : far_rest).push_back(b);
+    }
+    const std::vector<int32_t>& rest = opts.o.exact_lowrank ? far_rest : far;
+    for (auto& p : partition(far_exact, true)) jobs.push_back(Job{true, std::move(p), true});
+    for (auto& p : partition(rest, true)) jobs.push_back(Job{true, std::move(p)});
     c.st.t_host[2] += now_seconds() - tp;
     return jobs;
   };
@@ -1795,6 +2216,7 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     }
     ch->blocks = job.blocks;
     ch->near = !job.far;
+    ch->share_s1 = !(job.far && own_inputs);
     const bool features = job.far && (predict || collect);
     if (overlap) {
       next = std::async(std::launch::async, build, std::move(ch), features);
@@ -1847,7 +2269,10 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
           c.st.t_predict += now_seconds() - tq;
         }
         outs.emplace_back();
-        compress_chunk(c, ch, w0, outs.back());
+        if (jobs[k].exact) compress_chunk_exact(c, ch, outs.back());
+        else if (opts.o.scheme != HMAT_SCHEME_RANDOMIZED) compress_chunk_iter(c, ch, outs.back());
+        else if (opts.o.k_fixed > 0) compress_chunk_fixed(c, ch, outs.back());
+        else compress_chunk(c, ch, w0, outs.back());
         if (collect) {
           const FarOut& fo = outs.back();
           C->features.feats.insert(C->features.feats.end(), ch.feats.begin(), ch.feats.end());

@@ -247,6 +247,7 @@ void Tree::ensure_device(hipStream_t s) {
   dev->brow_blk.upload(brow_blk, s);
   dev->bcol_ptr.upload(bcol_ptr, s);
   dev->bcol_blk.upload(bcol_blk, s);
+  dev->perm.upload(perm, s);
   std::vector<double> xp(3 * n);
   for (int64_t i = 0; i < n; ++i)
     for (int k = 0; k < 3; ++k) xp[3 * i + k] = xyz[3 * int64_t(perm[i]) + k];

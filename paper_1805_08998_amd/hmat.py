@@ -17,6 +17,7 @@ HMAT_OK, HMAT_ERR_ARG, HMAT_ERR_TREE_MISMATCH, HMAT_ERR_NOT_CONVERGED = 0, 1, 2,
 HMAT_ERR_DEVICE, HMAT_ERR_OOM, HMAT_ERR_INTERNAL = 4, 5, 6
 HMAT_FP64, HMAT_FP32_APPLY, HMAT_BF16_SKETCH = 0, 1, 2
 HMAT_RANK_ADAPTIVE, HMAT_RANK_PREDICT = 0, 1
+HMAT_SCHEME_RANDOMIZED, HMAT_SCHEME_ACA, HMAT_SCHEME_LANCZOS = 0, 1, 2
 KERN_NAMES = ["term_reduce", "leaf_reduce", "subtree_expand", "gather", "compress", "fused_terms", "fused_terms4",
               "near_direct"]
 # device kernel(s) of each timed family
@@ -50,7 +51,8 @@ class hmat_stats(C.Structure):
                 ("kern_flops", C.c_double * 8), ("t_host", C.c_double * 8), ("t_alloc", C.c_double),
                 ("n_malloc", C.c_int64), ("n_cache_release", C.c_int64), ("target_passes", C.c_int64),
                 ("streams_used", C.c_int32), ("pad_s", C.c_int32), ("n_near_direct", C.c_int64),
-                ("t_near_panels", C.c_double), ("n_terms", C.c_int64), ("n_leaf_pairs", C.c_int64)]
+                ("t_near_panels", C.c_double), ("n_terms", C.c_int64), ("n_leaf_pairs", C.c_int64),
+                ("scheme_steps", C.c_int64), ("n_exact_lowrank", C.c_int64), ("n_svd_sweep_cap", C.c_int64)]
 
     def as_dict(self):
         d = {}
@@ -65,7 +67,9 @@ class hmat_opts(C.Structure):
                 ("probes", C.c_int32), ("max_growth", C.c_int32), ("p_l", C.c_int32), ("time_kernels", C.c_int32),
                 ("delta", C.c_double), ("seed", C.c_uint64), ("stream", C.c_void_p),
                 ("rank_model", C.c_void_p), ("stats", C.POINTER(hmat_stats)),
-                ("workspace_limit", C.c_int64), ("streams", C.c_int32), ("pad", C.c_int32)]
+                ("workspace_limit", C.c_int64), ("streams", C.c_int32), ("scheme", C.c_int32),
+                ("k_fixed", C.c_int32), ("subspace_iters", C.c_int32), ("exact_lowrank", C.c_int32),
+                ("pad2", C.c_int32)]
 
 
 class hmat_kernel(C.Structure):
@@ -106,6 +110,8 @@ _SIGS = {
     "hmat_multiply": (C.c_int32, [_P, _P, C.c_double, C.POINTER(hmat_opts), _PP]),
     "hmat_multiply_batched": (C.c_int32, [_PP, _PP, C.c_int32, C.c_double, C.POINTER(hmat_opts), _PP, _I32]),
     "hmat_to_dense": (C.c_int32, [_P, _D, C.c_int64, C.c_int32]),
+    "hmat_matvec": (C.c_int32, [_P, C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64, _P, C.c_int64, _P]),
+    "hmat_error_estimate": (C.c_int32, [_P, _P, _P, _P, C.c_int32, C.c_int32, _P, _D, _D]),
     "hmat_block_count": (C.c_int32, [_P, _I64]),
     "hmat_block_get": (C.c_int32, [_P, C.c_int64, C.POINTER(hmat_block_desc), _D, _D]),
     "hmat_export": (C.c_int32, [_P, _I32, _I64, _D, _I64]),
@@ -127,9 +133,17 @@ _lib = None
 
 
 def lib():
-    """Loads libhmat.so from the package directory (raises if it is missing)."""
+    """Loads libhmat.so from the package directory (raises if it is missing).
+
+    The library and PyTorch must share one HIP runtime: torch (when installed) is
+    imported first, so that libhmat.so binds to the runtime torch has loaded instead of
+    bringing in a second one that torch then fails to initialise."""
     global _lib
     if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1805_08998_amd.build`")
         L = C.CDLL(LIB_PATH)
@@ -207,20 +221,25 @@ def hmat_tree_blocks(t):
 
 
 # ---------------------------------------------------------------- options
+def _set_fields(o, kw):
+    names = {f for f, _ in type(o)._fields_}
+    for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"{type(o).__name__} has no field {k!r}")
+        setattr(o, k, v)
+    return o
+
+
 def hmat_opts_default(**kw):
     o = hmat_opts()
     lib().hmat_opts_default(C.byref(o))
-    for k, v in kw.items():
-        setattr(o, k, v)
-    return o
+    return _set_fields(o, kw)
 
 
 def hmat_train_opts_default(**kw):
     o = hmat_train_opts()
     lib().hmat_train_opts_default(C.byref(o))
-    for k, v in kw.items():
-        setattr(o, k, v)
-    return o
+    return _set_fields(o, kw)
 
 
 # ---------------------------------------------------------------- matrices
@@ -264,6 +283,22 @@ def hmat_multiply_batched(As, Bs, eps, opts=None):
     if code != HMAT_OK and not np.any(st != HMAT_OK):
         _check(code)  # the call itself failed (arguments, device)
     return [C.c_void_p(x) for x in c], st
+
+
+def hmat_matvec(m, x_ptr, ldx, y_ptr, ldy, nvec, trans=0, order=1, stream=None):
+    """y = M x (trans 0) or M^T x (trans 1) for nvec column-major device vectors at the
+    device addresses x_ptr, y_ptr (enqueued on `stream`, a hipStream_t as int or None)."""
+    _check(lib().hmat_matvec(m, trans, order, nvec, C.c_void_p(x_ptr), ldx, C.c_void_p(y_ptr), ldy,
+                             C.c_void_p(stream or 0)))
+
+
+def hmat_error_estimate(Cm, Am, Bm, x0_ptr, p, iters, stream=None):
+    """(estimate of ||C - A B||_F, estimate of ||A B||_F) from the device start block
+    at x0_ptr (n x p, column-major, cluster order)."""
+    err, nrm = C.c_double(), C.c_double()
+    _check(lib().hmat_error_estimate(Cm, Am, Bm, C.c_void_p(x0_ptr), p, iters, C.c_void_p(stream or 0),
+                                     C.byref(err), C.byref(nrm)))
+    return err.value, nrm.value
 
 
 def hmat_to_dense(m, n, order=1):

@@ -191,3 +191,27 @@ def test_lowrank_svd_equals_dense_truncation():
         Ld, Rd, _, k = truncate(L @ R.T, eps)
         assert Lo.shape[1] == k
         assert np.linalg.norm(Lo @ Ro.T - Ld @ Rd.T) <= 1e-12 * np.linalg.norm(L @ R.T)
+
+
+# ---------------------------------------------------------------- subspace estimator
+def test_subspace_frobenius_pins():
+    from oracle.product import subspace_frobenius
+    rng = np.random.default_rng(13)
+    # rank-6 operator: a block of p >= 6 directions captures all of it -> exactly ||E||_F
+    E = rng.standard_normal((80, 6)) @ rng.standard_normal((6, 70))
+    est = subspace_frobenius(lambda X: E @ X, lambda Y: E.T @ Y, rng.standard_normal((70, 8)), 3)
+    assert est == pytest.approx(np.linalg.norm(E), rel=1e-12)
+    # decaying spectrum, p = 5: converges to the norm of the top-5 part, below ||E||_F
+    U = np.linalg.qr(rng.standard_normal((60, 20)))[0]
+    V = np.linalg.qr(rng.standard_normal((50, 20)))[0]
+    s = 0.5 ** np.arange(20)
+    E = U @ np.diag(s) @ V.T
+    est = subspace_frobenius(lambda X: E @ X, lambda Y: E.T @ Y, rng.standard_normal((50, 5)), 12)
+    assert est == pytest.approx(np.sqrt(np.sum(s[:5] ** 2)), rel=1e-8)
+    assert est < np.linalg.norm(E)
+    # the transpose must be E^T: with E itself in its place (a transposed-operand slip) the
+    # estimate is wrong
+    Esq = E[:50]
+    good = subspace_frobenius(lambda X: Esq @ X, lambda Y: Esq.T @ Y, rng.standard_normal((50, 5)), 12)
+    wrong = subspace_frobenius(lambda X: Esq @ X, lambda Y: Esq @ Y, rng.standard_normal((50, 5)), 12)
+    assert abs(wrong - good) > 1e-3 * good
