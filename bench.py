@@ -267,6 +267,12 @@ def main():
                     help="timed plain float64 products after the learned or mixed ones (default: min(--steps, 5))")
     ap.add_argument("--eps", type=float, default=None,
                     help="product accuracy (default: the workload's); the predictor is then trained at it too")
+    ap.add_argument("--scheme", default="randomized", choices=["randomized", "aca", "lanczos"],
+                    help="low-rank scheme of the farfield blocks (Section 4); aca and lanczos run plain")
+    ap.add_argument("--k-fixed", type=int, default=0,
+                    help="fixed-rank mode: ACA/Lanczos stop after k steps, randomized runs Algorithm 9")
+    ap.add_argument("--exact-lowrank", action="store_true",
+                    help="targets without H-pairs are truncated exactly by Algorithm 5")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -292,6 +298,12 @@ def main():
               "is not known. Small batches are covered by tests/test_gpu_batched.py.", file=sys.stderr)
         sys.exit(2)
     w = CONFIGS[args.workload]
+    scheme_code = {"randomized": H.HMAT_SCHEME_RANDOMIZED, "aca": H.HMAT_SCHEME_ACA,
+                   "lanczos": H.HMAT_SCHEME_LANCZOS}[args.scheme]
+    if (args.scheme != "randomized" or args.k_fixed) and args.mode != "plain":
+        log(f"[bench] scheme {args.scheme}, k_fixed {args.k_fixed}: runs in plain mode (the predictor sizes "
+            "the first sketch of the adaptive randomized scheme only)")
+        args.mode = "plain"
     if args.eps is not None:
         w = dataclasses.replace(w, eps=args.eps)
     model = None
@@ -320,6 +332,9 @@ def main():
             o.rank_mode = H.HMAT_RANK_PREDICT
             o.rank_model = model
         o.time_kernels = 1 if time_kernels else 0
+        o.scheme = scheme_code
+        o.k_fixed = args.k_fixed
+        o.exact_lowrank = 1 if args.exact_lowrank else 0
         o.stats = ctypes.pointer(st)
         ts = time.perf_counter()
         C, code = H.hmat_multiply(A, B, w.eps, o, allow_not_converged=True)
@@ -440,7 +455,8 @@ def main():
         "config": {"workload": w.name, "n": w.n, "geometry": w.geometry, "jitter": w.jitter, "leaf": w.leaf,
                    "eta": w.eta, "split": "midpoint" if w.split == 0 else "median",
                    "kernels": [f"{w.kernel_a.kind}+{w.kernel_a.shift}I", f"{w.kernel_b.kind}+{w.kernel_b.shift}I"],
-                   "eps": w.eps, "eps_in": w.eps_in, "mode": args.mode, "seconds_per_product": t,
+                   "eps": w.eps, "eps_in": w.eps_in, "mode": args.mode, "scheme": args.scheme,
+                   "k_fixed": args.k_fixed, "exact_lowrank": bool(args.exact_lowrank), "seconds_per_product": t,
                    "alg_flops": flops, "alg_bytes": st["bytes_alg"], "predictor": train_info,
                    "timing": spread, "plain": plain},
         "roofline": roofline,
