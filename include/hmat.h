@@ -372,6 +372,24 @@ hmat_status hmat_matvec(hmat M, int32_t trans, int32_t order, int32_t nvec, cons
                         double* y, int64_t ldy, void* stream);
 
 /*
+ * hmat_matvec for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): same
+ * arguments, results bit-identical to hmat_matvec, but the scratch lives in a
+ * static device array of HMAT_MATVEC_NOALLOC_BYTES that each GPU the library
+ * runs on holds until the process ends; no hipMalloc, hipFree or allocating
+ * library routine is called. Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (on different streams, or from several host
+ * threads without ordering) race and give wrong results. The tree's device copy
+ * must already exist (any product, assembly or hmat_matvec on M creates it).
+ * Errors: those of hmat_matvec, and HMAT_ERR_ARG when the scratch (8 bytes per
+ * block of the tree plus 8 nvec bytes per farfield rank unit) exceeds
+ * HMAT_MATVEC_NOALLOC_BYTES.
+ */
+#define HMAT_MATVEC_NOALLOC_BYTES (64LL << 20)
+hmat_status hmat_matvec_noalloc(hmat M, int32_t trans, int32_t order, int32_t nvec, const double* x, int64_t ldx,
+                                double* y, int64_t ldy, void* stream);
+
+/*
  * Accuracy estimate of a product C ~ A B (the error estimator of the paper's
  * numerical examples): subspace iteration on E v = C v - A (B v), whose
  * products are three calls of Algorithm 2. From the start block X0 (DEVICE

@@ -12,6 +12,8 @@
 // Vectors are in the caller's point order (order 0: original indices, gathered
 // and scattered through the permutation) or in cluster order (order 1).
 #include <algorithm>
+#include <mutex>
+#include <string>
 
 #include "hmat_internal.h"
 #include "device_common.h"
@@ -190,4 +192,51 @@ void matvec_launch(const HMat* M, int32_t trans, int32_t order, int32_t nvec, co
   HM_CHECK_HIP(hipGetLastError());
 }
 
+// ---------------------------------------------------------------- no-allocation variant
+// Scratch of hmat_matvec_noalloc: a static device array, one copy per GPU the library
+// runs on, allocated with the code object and held until the process ends. In host code
+// `scratch` only names the symbol; its device address on each GPU comes from
+// hipGetSymbolAddress (once per device, with that device current).
+static __device__ __align__(256) double scratch[HMAT_MATVEC_NOALLOC_BYTES / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+double* scratch_of_device(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  HM_REQUIRE(dev >= 0 && dev < kMaxDevices, HMAT_ERR_ARG, "device id out of range");
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    HM_CHECK_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_dev[dev] = static_cast<double*>(ptr);
+  }
+  return g_scratch_dev[dev];
+}
+}  // namespace
+
 }  // namespace hm
+
+extern "C" hmat_status hmat_matvec_noalloc(hmat mh, int32_t trans, int32_t order, int32_t nvec, const double* x,
+                                           int64_t ldx, double* y, int64_t ldy, void* stream) {
+  using namespace hm;
+  try {
+    HMat* M = check_matvec_args(mh, trans, order, nvec, x, ldx, y, ldy);
+    const int64_t need = matvec_scratch_doubles(M, nvec) * int64_t(sizeof(double));
+    HM_REQUIRE(need <= int64_t(HMAT_MATVEC_NOALLOC_BYTES), HMAT_ERR_ARG,
+               "hmat_matvec_noalloc needs " + std::to_string(need) + " bytes of scratch, above its static " +
+                   std::to_string(int64_t(HMAT_MATVEC_NOALLOC_BYTES)) + " (use hmat_matvec or fewer vectors)");
+    int dev = 0;
+    HM_CHECK_HIP(hipGetDevice(&dev));
+    double* sp = scratch_of_device(dev);
+    matvec_launch(M, trans, order, nvec, x, ldx, y, ldy, sp, reinterpret_cast<hipStream_t>(stream));
+    return HMAT_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return HMAT_ERR_INTERNAL;
+  }
+}

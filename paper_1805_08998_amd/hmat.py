@@ -18,6 +18,7 @@ HMAT_ERR_DEVICE, HMAT_ERR_OOM, HMAT_ERR_INTERNAL = 4, 5, 6
 HMAT_FP64, HMAT_FP32_APPLY, HMAT_BF16_SKETCH = 0, 1, 2
 HMAT_RANK_ADAPTIVE, HMAT_RANK_PREDICT = 0, 1
 HMAT_SCHEME_RANDOMIZED, HMAT_SCHEME_ACA, HMAT_SCHEME_LANCZOS = 0, 1, 2
+HMAT_MATVEC_NOALLOC_BYTES = 64 << 20  # static scratch of hmat_matvec_noalloc per GPU
 KERN_NAMES = ["term_reduce", "leaf_reduce", "subtree_expand", "gather", "compress", "fused_terms", "fused_terms4",
               "near_direct"]
 # device kernel(s) of each timed family
@@ -112,6 +113,7 @@ _SIGS = {
     "hmat_to_dense": (C.c_int32, [_P, _D, C.c_int64, C.c_int32]),
     "hmat_matvec": (C.c_int32, [_P, C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64, _P, C.c_int64, _P]),
     "hmat_error_estimate": (C.c_int32, [_P, _P, _P, _P, C.c_int32, C.c_int32, _P, _D, _D]),
+    "hmat_matvec_noalloc": (C.c_int32, [_P, C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64, _P, C.c_int64, _P]),
     "hmat_block_count": (C.c_int32, [_P, _I64]),
     "hmat_block_get": (C.c_int32, [_P, C.c_int64, C.POINTER(hmat_block_desc), _D, _D]),
     "hmat_export": (C.c_int32, [_P, _I32, _I64, _D, _I64]),
@@ -290,6 +292,12 @@ def hmat_matvec(m, x_ptr, ldx, y_ptr, ldy, nvec, trans=0, order=1, stream=None):
     device addresses x_ptr, y_ptr (enqueued on `stream`, a hipStream_t as int or None)."""
     _check(lib().hmat_matvec(m, trans, order, nvec, C.c_void_p(x_ptr), ldx, C.c_void_p(y_ptr), ldy,
                              C.c_void_p(stream or 0)))
+
+
+def hmat_matvec_noalloc(m, x_ptr, ldx, y_ptr, ldy, nvec, trans=0, order=1, stream=None):
+    """hmat_matvec with its scratch in the library's static device array (no allocation)."""
+    _check(lib().hmat_matvec_noalloc(m, trans, order, nvec, C.c_void_p(x_ptr), ldx, C.c_void_p(y_ptr), ldy,
+                                     C.c_void_p(stream or 0)))
 
 
 def hmat_error_estimate(Cm, Am, Bm, x0_ptr, p, iters, stream=None):
