@@ -164,9 +164,11 @@ def cpu_baseline(H, tree, A, B, C, eps, seconds=20.0, max_rows=256, seed=0):
     return out
 
 
-def train_predictor(H, configs, names, epochs, cache=None, eps=None):
-    """Rank predictor trained on the farfield ranks of plain products of other
-    workloads (untimed), at their own accuracy or at `eps` when given. Returns
+def train_predictor(H, configs, names, epochs, cache=None, eps=None, target="widths"):
+    """Rank predictor trained on plain products of other workloads (untimed), at their
+    own accuracy or at `eps` when given. Its label per farfield block is the sketch
+    width at which the residual check passed (target "widths": the width a first
+    sketch needs to avoid growth rounds) or the block's final rank ("ranks"). Returns
     the model handle and a summary. With `cache`, the training features are read
     from that .npz file when it exists (written by an earlier run with the same
     options), else computed and saved there."""
@@ -188,6 +190,8 @@ def train_predictor(H, configs, names, epochs, cache=None, eps=None):
         o.stats = ctypes.pointer(st)
         C, _ = H.hmat_multiply(A, B, wl.eps if eps is None else eps, o, allow_not_converged=True)
         f, r = H.hmat_product_features(C)
+        if target == "widths":
+            r = H.hmat_product_widths(C)
         feats.append(f)
         ranks.append(r)
         for h in ([A, C] if wl.same_ab else [A, B, C]):
@@ -206,8 +210,8 @@ def train_predictor(H, configs, names, epochs, cache=None, eps=None):
     rmse = float(np.sqrt(np.mean((pred - r) ** 2)))
     log(f"[bench] predictor trained on {len(r)} blocks in {t2 - t1:.1f}s (data {t1 - t0:.1f}s), "
         f"loss {losses[0]:.4f} -> {losses[-1]:.4f}, rank rmse {rmse:.2f}")
-    return model, {"train_on": names, "train_eps": eps, "samples": int(len(r)), "epochs": epochs, "train_seconds": t2 - t1,
-                   "rank_rmse_train": rmse, "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
+    return model, {"train_on": names, "train_eps": eps, "target": target, "samples": int(len(r)), "epochs": epochs,
+                   "train_seconds": t2 - t1, "rank_rmse_train": rmse, "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
 
 
 def copy_probe():
@@ -261,6 +265,8 @@ def main():
     ap.add_argument("--train-on", default="sphere64k,ellipsoid256k",
                     help="workloads whose plain products provide the predictor's training data")
     ap.add_argument("--train-epochs", type=int, default=30)
+    ap.add_argument("--train-target", default="widths", choices=["widths", "ranks"],
+                    help="predictor label: sketch width at which the check passed, or final rank")
     ap.add_argument("--features-cache", default=None,
                     help=".npz file of predictor training features (read if present, else written)")
     ap.add_argument("--compare-steps", type=int, default=None,
@@ -310,7 +316,7 @@ def main():
     train_info = None
     if args.mode == "learned":
         model, train_info = train_predictor(H, CONFIGS, args.train_on.split(","), args.train_epochs,
-                                            args.features_cache, eps=args.eps)
+                                            args.features_cache, eps=args.eps, target=args.train_target)
     pts = w.points()
     t0 = time.perf_counter()
     tree = H.hmat_build_tree(pts, w.leaf, w.eta, w.split)
@@ -360,6 +366,7 @@ def main():
         log(f"[bench] step {i}: {dt:.3f}s batches {st['n_batches']} restrict {st['t_restrict']:.3f} "
             f"near {st['t_near']:.3f} sketch {st['t_sketch']:.3f} project {st['t_project']:.3f} "
             f"grown {st['n_grown_blocks']} fallback {st['n_fallback']} columns {st['sketch_columns']} "
+            f"growth {st['t_growth']:.3f}s "
             f"alloc {st['t_alloc']:.3f}s releases {st['n_cache_release']}")
     t = sum(times) / len(times)
     st = stats[-1]
@@ -382,6 +389,7 @@ def main():
             H.hmat_destroy(Cp)
             pt.append(dt)
             log(f"[bench] plain step {i}: {dt:.3f}s batches {pst['n_batches']} grown {pst['n_grown_blocks']} "
+                f"growth {pst['t_growth']:.3f}s "
                 f"columns {pst['sketch_columns']} sketch {pst['t_sketch']:.3f} project {pst['t_project']:.3f}")
         tp = sum(pt) / len(pt)
         plain = {"seconds_per_product": tp, "median_s": float(np.median(pt)), "min_s": min(pt), "max_s": max(pt),

@@ -196,6 +196,10 @@ typedef struct {
   int64_t scheme_steps;
   int64_t n_exact_lowrank;
   int64_t n_svd_sweep_cap;
+  /* seconds spent in the growth rounds of the adaptive randomized scheme (extra probes,
+   * orthogonalisation and projections after the first residual check): the most that a
+   * better first sketch width (HMAT_RANK_PREDICT) can save */
+  double t_growth;
 } hmat_stats;
 
 /* Kernel families of hmat_stats.kern_* */
@@ -506,6 +510,13 @@ hmat_status hmat_rank_model_grad(hmat_rank_model model, const float* feats, cons
  * query it).
  */
 hmat_status hmat_product_features(hmat C, float* feats, float* ranks, int64_t* count);
+/*
+ * Sketch widths of the same blocks (same order as hmat_product_features): the
+ * number of orthonormal sketch columns at which the residual check passed, the
+ * width a first sketch must have to need no growth round. widths: host
+ * float[n_far]; *count as above.
+ */
+hmat_status hmat_product_widths(hmat C, float* widths, int64_t* count);
 
 #ifdef __cplusplus
 }

@@ -207,6 +207,32 @@ class LeafStrips:
         return S
 
 
+def exact_block_chunked(sa: LeafStrips, sb: LeafStrips, r0, r1, c0, c1, chunk=8192):
+    """(A_H B_H)[r0:r1, c0:c1] = sum over column ranges K of A_H[rows, K] @ B_H[K, cols]:
+    the strip product of exact_block_strips with the inner dimension taken in pieces of
+    `chunk`, so that host memory stays at (r1 - r0 + c1 - c0) * chunk doubles."""
+    m, n = r1 - r0, c1 - c0
+    D = np.zeros((m, n))
+    rows = sa.rows_needed(r0, r1)
+    cols = sb.cols_needed(c0, c1)
+    for k0 in range(0, sa.n, chunk):
+        k1 = min(sa.n, k0 + chunk)
+        As = np.zeros((m, k1 - k0))
+        for i in rows[(sa.c0[rows] < k1) & (sa.c1[rows] > k0)]:
+            L = sa.leaf(i)
+            lo, hi = max(r0, sa.r0[i]), min(r1, sa.r1[i])
+            cl, ch = max(k0, sa.c0[i]), min(k1, sa.c1[i])
+            As[lo - r0:hi - r0, cl - k0:ch - k0] = L[lo - sa.r0[i]:hi - sa.r0[i], cl - sa.c0[i]:ch - sa.c0[i]]
+        Bs = np.zeros((k1 - k0, n))
+        for i in cols[(sb.r0[cols] < k1) & (sb.r1[cols] > k0)]:
+            L = sb.leaf(i)
+            rl, rh = max(k0, sb.r0[i]), min(k1, sb.r1[i])
+            lo, hi = max(c0, sb.c0[i]), min(c1, sb.c1[i])
+            Bs[rl - k0:rh - k0, lo - c0:hi - c0] = L[rl - sb.r0[i]:rh - sb.r0[i], lo - sb.c0[i]:hi - sb.c0[i]]
+        D += As @ Bs
+    return D
+
+
 def oracle_block(sa: LeafStrips, sb: LeafStrips, r0, r1, c0, c1, kind, eps):
     """The oracle's answer for one leaf of the product: the exact block and, for a
     farfield leaf, its singular values and epsilon-rank (Eckart-Young)."""

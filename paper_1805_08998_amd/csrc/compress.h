@@ -37,6 +37,8 @@ struct CTarget {
   int64_t out_off;     // element offset of the output L (then R) in the result pool
   int32_t block;       // block id
   int32_t w0;          // initial sketch width of this target (b0 or predicted)
+  int32_t svd_capped;  // 1: the core's Jacobi iteration reached its sweep cap
+  int32_t pad;
 };
 
 constexpr int CAPMAX_CORE = 64;  // largest column count of the per-target panels and cores

@@ -196,13 +196,16 @@ __global__ void __launch_bounds__(NT) k_core(CTarget* __restrict__ tg, int nt, i
     const int lane = threadIdx.x;
     for (int i = 0; i < r; ++i)
       if (lane < r) J[i * LD + lane] = (lane == i) ? 1.0 : 0.0;
-    for (int sweep = 0; sweep < 40; ++sweep) {
+    int capped = 1;
+    for (int sweep = 0; sweep < 60; ++sweep) {
       int rotated = 0;
       for (int p = 0; p < r - 1; ++p)
         for (int q = p + 1; q < r; ++q) {
           double mp = lane < r ? M[p * LD + lane] : 0.0;
           double mq = lane < r ? M[q * LD + lane] : 0.0;
-          double a = wave_sum(mp * mp), b = wave_sum(mq * mq), c = wave_sum(mp * mq);
+          // one rotation for the whole wave: the angle must not differ between lanes
+          const double a = wave_uniform(wave_sum(mp * mp)), b = wave_uniform(wave_sum(mq * mq)),
+                       c = wave_uniform(wave_sum(mp * mq));
           if (fabs(c) <= 1e-15 * sqrt(a * b) || c == 0.0) continue;
           rotated = 1;
           double zeta = (b - a) / (2.0 * c);
@@ -216,8 +219,12 @@ __global__ void __launch_bounds__(NT) k_core(CTarget* __restrict__ tg, int nt, i
             J[q * LD + lane] = sn * jp + cs * jq;
           }
         }
-      if (!rotated) break;
+      if (!rotated) {
+        capped = 0;
+        break;
+      }
     }
+    if (lane == 0) T.svd_capped = capped;
     for (int j = 0; j < r; ++j) {
       double mj = lane < r ? M[j * LD + lane] : 0.0;
       double s2 = wave_sum(mj * mj);

@@ -15,6 +15,16 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Lane 0's value of v in every lane. A wave_sum result can differ in its last bits from
+// lane to lane (measured on gfx950 for operands spanning many orders of magnitude), so a
+// value that steers per-lane work which must agree across the wave (a rotation angle, a
+// skip test) is taken from one lane.
+__device__ __forceinline__ double wave_uniform(double v) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
 // Sum over a workgroup of NT threads (NT multiple of 64); `red` holds NT/64 doubles.
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* red) {

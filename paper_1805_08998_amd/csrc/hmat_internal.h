@@ -143,6 +143,7 @@ void tree_release(Tree* t);
 struct ProductFeatures {
   std::vector<float> feats;  // n_far x 6
   std::vector<float> ranks;
+  std::vector<float> widths;  // sketch columns at which the residual check passed
 };
 
 struct HMat {

@@ -461,4 +461,14 @@ hmat_status hmat_product_features(hmat C, float* feats, float* ranks, int64_t* c
   API_END
 }
 
+hmat_status hmat_product_widths(hmat C, float* widths, int64_t* count) {
+  API_BEGIN
+  HM_REQUIRE(C && count, HMAT_ERR_ARG, "NULL argument");
+  const ProductFeatures& pf = reinterpret_cast<HMat*>(C)->features;
+  const int64_t nf = int64_t(pf.widths.size());
+  if (widths) std::memcpy(widths, pf.widths.data(), 4 * nf);
+  *count = nf;
+  API_END
+}
+
 }  // extern "C"

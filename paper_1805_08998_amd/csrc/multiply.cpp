@@ -1219,6 +1219,7 @@ void run_pass(Ctx& c, Chunk& ch, const std::vector<TDesc>& td, bool trans, bool 
 struct FarOut {
   DevBuf<double> buf;
   std::vector<int32_t> blocks, ranks;
+  std::vector<int32_t> widths;  // randomized scheme: columns of Q when the residual check passed
   std::vector<uint8_t> done;
   std::vector<int64_t> offs;
   int64_t len = 0;
@@ -1405,6 +1406,7 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
     c.st.n_growth_rounds++;
     c.st.n_grown_blocks += cnt;
     double ta = now_seconds();
+    const double tg0 = ta;
     dt.upload(h, s);
     std::vector<int> r_old(nt);
     for (int i = 0; i < nt; ++i) r_old[i] = h[i].r;
@@ -1435,6 +1437,7 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
     launch_probe_residual(dt.p, nt, cp, s);
     c.timer.end();
     c.st.t_project += now_seconds() - tb;
+    c.st.t_growth += now_seconds() - tg0;
   }
   double t3 = now_seconds();
   launch_check(dt.p, nt, cp, pending.p, s);
@@ -1446,12 +1449,15 @@ void compress_chunk(Ctx& c, Chunk& ch, const std::vector<int32_t>& w0, FarOut& o
   fetch();
   out.blocks.clear();
   out.ranks.clear();
+  out.widths.clear();
   out.done.clear();
   out.offs.clear();
   out.len = 0;
   for (int i = 0; i < nt; ++i) {
     CTarget& T = h[i];
+    out.widths.push_back(T.r);
     if (!T.done) c.st.n_not_converged++;
+    if (T.svd_capped) c.st.n_svd_sweep_cap++;
     if (T.rounds > 0 && c.opts.o.rank_mode == HMAT_RANK_PREDICT) c.st.n_fallback++;
     out.blocks.push_back(T.block);
     out.ranks.push_back(T.k);
@@ -1593,6 +1599,7 @@ void compress_chunk_exact(Ctx& c, Chunk& ch, FarOut& out) {
     out.len += int64_t(T.k) * (T.m + T.n);
     c.st.rank_hist[std::min(T.k, 64)]++;
     c.st.n_exact_lowrank++;
+    if (T.svd_capped) c.st.n_svd_sweep_cap++;
     charge_far(c, ch, i, T.block, T.m, T.n, T.k);
   }
   out.buf.alloc(size_t(std::max<int64_t>(out.len, 1)));
@@ -2277,6 +2284,8 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
           const FarOut& fo = outs.back();
           C->features.feats.insert(C->features.feats.end(), ch.feats.begin(), ch.feats.end());
           for (int32_t k : fo.ranks) C->features.ranks.push_back(float(k));
+          for (size_t j = 0; j < fo.ranks.size(); ++j)
+            C->features.widths.push_back(float(j < fo.widths.size() ? fo.widths[j] : fo.ranks[j]));
         }
       }
       chp->mark_done(s);

@@ -390,7 +390,7 @@ __global__ void __launch_bounds__(NT) k_iter_svd(ITarget* __restrict__ tg, int c
     double total = 0.0;
     for (int j = 0; j < r; ++j) {
       const double x = lane < r ? M[j * r + lane] : 0.0;
-      total += wave_sum(x * x);
+      total += wave_uniform(wave_sum(x * x));
     }
     int sweeps = -1;
     for (int sweep = 0; sweep < JACOBI_SWEEPS; ++sweep) {
@@ -399,7 +399,9 @@ __global__ void __launch_bounds__(NT) k_iter_svd(ITarget* __restrict__ tg, int c
         for (int q = p + 1; q < r; ++q) {
           const double mp = lane < r ? M[p * r + lane] : 0.0;
           const double mq = lane < r ? M[q * r + lane] : 0.0;
-          const double a = wave_sum(mp * mp), b = wave_sum(mq * mq), c = wave_sum(mp * mq);
+          // one rotation for the whole wave: the angle must not differ between lanes
+          const double a = wave_uniform(wave_sum(mp * mp)), b = wave_uniform(wave_sum(mq * mq)),
+                       c = wave_uniform(wave_sum(mp * mq));
           // converged pair: orthogonal to working precision, or both columns at the
           // rounding level of the whole core
           if (c == 0.0 || fabs(c) <= 1e-15 * sqrt(a * b) || fabs(c) <= 1e-32 * total) continue;

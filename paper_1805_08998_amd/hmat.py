@@ -53,7 +53,8 @@ class hmat_stats(C.Structure):
                 ("n_malloc", C.c_int64), ("n_cache_release", C.c_int64), ("target_passes", C.c_int64),
                 ("streams_used", C.c_int32), ("pad_s", C.c_int32), ("n_near_direct", C.c_int64),
                 ("t_near_panels", C.c_double), ("n_terms", C.c_int64), ("n_leaf_pairs", C.c_int64),
-                ("scheme_steps", C.c_int64), ("n_exact_lowrank", C.c_int64), ("n_svd_sweep_cap", C.c_int64)]
+                ("scheme_steps", C.c_int64), ("n_exact_lowrank", C.c_int64), ("n_svd_sweep_cap", C.c_int64),
+                ("t_growth", C.c_double)]
 
     def as_dict(self):
         d = {}
@@ -129,6 +130,7 @@ _SIGS = {
     "hmat_rank_model_set": (C.c_int32, [_P, _F, C.c_int64]),
     "hmat_rank_model_grad": (C.c_int32, [_P, _F, _F, C.c_int64, _F, _F]),
     "hmat_product_features": (C.c_int32, [_P, _F, _F, _I64]),
+    "hmat_product_widths": (C.c_int32, [_P, _F, _I64]),
 }
 
 _lib = None
@@ -431,3 +433,13 @@ def hmat_product_features(Cm):
     r = np.empty(cnt.value, dtype=np.float32)
     _check(lib().hmat_product_features(Cm, _fp(f), _fp(r), C.byref(cnt)))
     return f, r
+
+
+def hmat_product_widths(Cm):
+    """Sketch widths at which the residual check passed, per farfield block (same order as
+    hmat_product_features)."""
+    cnt = C.c_int64(0)
+    _check(lib().hmat_product_widths(Cm, None, C.byref(cnt)))
+    w = np.empty(cnt.value, dtype=np.float32)
+    _check(lib().hmat_product_widths(Cm, _fp(w), C.byref(cnt)))
+    return w

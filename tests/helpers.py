@@ -79,22 +79,30 @@ def leaf_source(H, tree, M):
     return src
 
 
-def sampled_check(H, tree, A, B, C, eps, per_level=3, seed=0, max_rows=2048, log=print):
-    """Checks a stratified sample of C's leaves (per level and kind) against exact
-    blocks A_H[tau, :] B_H[:, sigma] built from strips. Returns the list of
-    (level, kind, rows, cols, err, rank, kstar, ok)."""
-    from oracle.product import check_block
+def sampled_check(H, tree, A, B, C, eps, per_level=3, seed=0, max_rows=2048, largest_rows=0, log=print):
+    """Checks a stratified sample of C's leaves (per level and kind, at most max_rows
+    rows) against exact blocks A_H[tau, :] B_H[:, sigma] built from strips, plus, per
+    level, the largest farfield leaf of at most `largest_rows` rows (0: none). Returns
+    the list of (level, kind, rows, cols, err, rank, kstar, ok)."""
+    from oracle.product import check_block, exact_block_chunked
     pa, pb, pc = leaf_source(H, tree, A), leaf_source(H, tree, B), leaf_source(H, tree, C)
     rng = np.random.default_rng(seed)
+    rows = pc.r1 - pc.r0
+    area = rows * (pc.c1 - pc.c0)
     out = []
     for L in np.unique(pc.level):
         for kind in (1, 2):
-            cand = np.nonzero((pc.level == L) & (pc.kind == kind) & (pc.r1 - pc.r0 <= max_rows))[0]
-            if cand.size == 0:
-                continue
-            for i in rng.choice(cand, min(per_level, cand.size), replace=False):
+            cand = np.nonzero((pc.level == L) & (pc.kind == kind) & (rows <= max_rows))[0]
+            pick = list(rng.choice(cand, min(per_level, cand.size), replace=False)) if cand.size else []
+            if kind == 1 and largest_rows:
+                big = np.nonzero((pc.level == L) & (pc.kind == 1) & (rows <= largest_rows))[0]
+                if big.size:
+                    j = int(big[np.argmax(area[big])])
+                    if j not in pick:
+                        pick.append(j)
+            for i in pick:
                 r0, r1, c0, c1 = pc.r0[i], pc.r1[i], pc.c0[i], pc.c1[i]
-                D = pa.row_strip(r0, r1) @ pb.col_strip(c0, c1)
+                D = exact_block_chunked(pa, pb, r0, r1, c0, c1)
                 d, U, V = H.hmat_block_get(C, int(i))
                 if kind == 1:
                     r = check_block(D, 1, eps, U=U, V=V)
@@ -103,4 +111,7 @@ def sampled_check(H, tree, A, B, C, eps, per_level=3, seed=0, max_rows=2048, log
                 out.append((int(L), kind, int(r1 - r0), int(c1 - c0), r.err, r.rank, r.kstar, r.ok))
                 log(f"  level {L} kind {kind} {r1 - r0}x{c1 - c0}: err {r.err:.3e} rank {r.rank} k* {r.kstar} "
                     f"{'ok' if r.ok else 'FAIL'}")
+    # leaves fetched for the strips are cached per source; free them
+    for src in (pa, pb, pc):
+        src.cache.clear()
     return out

@@ -171,6 +171,12 @@ def test_features(H, product_case):
     assert np.array_equal(np.sort(ranks), np.sort(far_ranks.astype(np.float32)))
     assert np.array_equal(np.sort(feats[:, 0]), np.sort(bl["level"][far].astype(np.float32)))
     assert np.all(np.isfinite(feats))
+    # sketch widths at which the residual check passed: at least the block's rank and at
+    # most the panel capacity; blocks that grew need more than the first width b0 (8)
+    widths = H.hmat_product_widths(C0)
+    assert widths.shape == ranks.shape
+    assert np.all(widths >= ranks) and np.all(widths <= 64)
+    assert int(np.sum(widths > 8)) <= st0.n_grown_blocks
     assert count_bad(H, t, C0, P, eps) == 0
     H.hmat_destroy(C0)
 

@@ -158,3 +158,9 @@ def test_leafstrips_and_oracle_block_equal_brute_force(small_case):
             assert np.allclose(s, sref, rtol=0, atol=1e-12 * sref[0])
         else:
             assert s is None and k is None
+    # the inner-dimension chunked strip product (bounded host memory at full size) equals
+    # the brute-force block for chunk sizes that cut leaves in the middle
+    from oracle.product import exact_block_chunked
+    for (r0, r1, c0, c1), chunk in (((37, 301, 1000, 1077), 500), ((0, 2048, 1900, 2048), 333), ((64, 128, 0, 64), 2048)):
+        D = exact_block_chunked(sa, sb, r0, r1, c0, c1, chunk=chunk)
+        assert np.abs(D - P[r0:r1, c0:c1]).max() <= 1e-13 * scale
