@@ -217,12 +217,16 @@ enum {
 
 typedef struct {
   int32_t precision;   /* HMAT_FP64 (default) or HMAT_FP32_APPLY */
-  int32_t rank_mode;   /* HMAT_RANK_ADAPTIVE (default) or HMAT_RANK_PREDICT */
+  int32_t rank_mode;   /* HMAT_RANK_ADAPTIVE (default) or HMAT_RANK_PREDICT: the model's output
+                          per farfield block is read as the sketch width the block needs; a
+                          prediction up to b0 + growth / 2 keeps the first width b0, above it the
+                          first width is the prediction plus p_l (rounded up to the 16-column
+                          pass granularity) */
   int32_t b0;          /* initial sketch width (default 8) */
   int32_t growth;      /* columns added per growth round (default 8) */
   int32_t probes;      /* probe columns of the a-posteriori check (default 8) */
   int32_t max_growth;  /* growth rounds before HMAT_ERR_NOT_CONVERGED (default 6) */
-  int32_t p_l;         /* oversampling added to a predicted rank above b0 (default 2) */
+  int32_t p_l;         /* oversampling added to a prediction that widens the first sketch (default 2) */
   int32_t time_kernels;/* 1: time every kernel launch with HIP events into stats */
   double delta;        /* residual target: E <= delta * eps * ||S||_F (default 0.2) */
   uint64_t seed;       /* random stream of the sketches (default 0x5eed) */

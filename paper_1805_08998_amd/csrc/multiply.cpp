@@ -1003,14 +1003,22 @@ void build_chunk(const Ctx& c, Chunk& ch, bool features) {
     TInfo& ti = ch.info[i];
     ti.block = b;
     ti.vbase = ch.vlen;
-    const bool direct = ch.near && c.m_of(b) <= NEAR_MAX && c.n_of(b) <= NEAR_MAX;
+    // the direct and fused kernels hold a term of width kl, kr <= 64 in registers and LDS
+    // tiles; a target with a wider term (a leaf cluster of duplicate points can exceed the
+    // leaf size) goes to term_reduce + gather
+    bool narrow_terms = true;
+    if (ch.near)
+      for (int32_t a = b; narrow_terms && a >= 0; a = t.b_parent[a])
+        for (int32_t j = c.group_ptr_h[a]; j < c.group_ptr_h[a + 1]; ++j)
+          if (c.sym[j].kl > NEAR_TERM_MAX || c.sym[j].kr > NEAR_TERM_MAX) narrow_terms = false;
+    const bool direct = ch.near && narrow_terms && c.m_of(b) <= NEAR_MAX && c.n_of(b) <= NEAR_MAX;
     ch.direct[i] = direct;
     const double mt = t.c_size[t.b_tau[b]], nt_ = t.c_size[t.b_sigma[b]];
     // the fused kernels serve nearfield targets that add pair results to the direct
     // kernel's output; farfield targets of every size use term_reduce + gather, which
     // measured faster on them than the fused kernels
-    const bool small1 = ch.near && mt <= FUSED_MAX && nt_ <= FUSED_MAX;
-    const bool small = small1 || (ch.near && mt <= FUSED4_MAX && nt_ <= FUSED4_MAX);
+    const bool small1 = ch.near && narrow_terms && mt <= FUSED_MAX && nt_ <= FUSED_MAX;
+    const bool small = small1 || (ch.near && narrow_terms && mt <= FUSED4_MAX && nt_ <= FUSED4_MAX);
     ch.is_small[i] = small1 ? 1 : small ? 2 : 0;
     if (small1) ch.small.push_back(i);
     else if (small) ch.small4.push_back(i);
@@ -2255,18 +2263,22 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
       } else {
         std::vector<int32_t> w0(ch.blocks.size(), opts.o.b0);
         if (predict) {
-          // learned initial widths: predicted rank plus oversampling, within the panel
-          // capacity (the residual check still grows the sketch where this is too small)
+          // learned initial widths: the prediction estimates the sketch width a block needs
+          // (the residual check still grows the sketch where it is too small)
           const double tq = now_seconds();
           std::vector<float> pred;
           predict_ranks(opts.o.rank_model, ch.feats, pred, s);
           for (size_t i = 0; i < w0.size(); ++i) {
             const int mn = std::min(c.m_of(ch.blocks[i]), c.n_of(ch.blocks[i]));
-            const double pr = std::isfinite(pred[i]) ? std::ceil(double(pred[i])) : double(opts.o.b0);
+            const double pv = std::isfinite(pred[i]) ? double(pred[i]) : double(opts.o.b0);
             const int g = opts.o.probes;
-            // a predicted rank within the plain initial width keeps that width (the plain
-            // first pass already covers it); above it the width is the prediction plus p_l
-            int w = pr <= opts.o.b0 ? opts.o.b0 : int(std::clamp(pr + opts.o.p_l, 1.0, double(64 - g)));
+            // a prediction below the middle of the first growth step keeps the plain initial
+            // width (its first pass most likely suffices; a regression trained mostly on
+            // blocks of that width scatters around it); above, the width is the prediction
+            // plus p_l
+            const double widen_at = opts.o.b0 + 0.5 * opts.o.growth;
+            int w = pv <= widen_at ? opts.o.b0
+                                   : int(std::clamp(std::ceil(pv) + opts.o.p_l, 1.0, double(64 - g)));
             // operator passes run PW columns at a time: widen the sketch as far as it
             // costs no extra pass of the sketch (w + g columns) or of the projection (w)
             const int up_s = (w + g + PW - 1) / PW * PW - g, up_p = (w + PW - 1) / PW * PW;

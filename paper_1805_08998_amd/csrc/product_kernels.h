@@ -7,6 +7,7 @@
 namespace hm {
 
 constexpr int PW = 16;  // columns per apply pass (wider passes are split)
+constexpr int NEAR_TERM_MAX = 64;  // largest term width (kl, kr) of a target of the direct nearfield kernel
 
 // One low-rank term of a sum-expression, L * core * R^T (Def. 3.1), stored
 // through views into the factor pools. Restriction to a sub-block (Algorithm 3)

@@ -183,32 +183,46 @@ def test_features(H, product_case):
 
 @pytest.mark.parametrize("eps", [1e-6, 1e-8])
 def test_learned_mode(H, product_case, eps):
-    """Trained on the plain product's own ranks, the learned mode keeps every block
-    within the bound; at eps = 1e-8, where ranks exceed the plain initial width,
-    it needs fewer growth rounds and fewer operator passes than the plain form;
-    at eps = 1e-6 (ranks around 6, inside the plain width) it costs at most 10 %
-    more passes."""
+    """The predictor is trained out of sample: on the sketch widths (hmat_product_widths)
+    of a product on other points (another jitter draw of the sphere and the ellipsoid
+    with axes 1, 0.7, 0.5), then applied to this product. The learned mode keeps every
+    block within the bound and grows at most half as many blocks as the plain form; at
+    eps = 1e-8, where most blocks grow, it also makes fewer operator passes (its wider
+    first sketches take passes of their own); at eps = 1e-6 at most 5 % more."""
+    from workloads import ellipsoid
     t, A, B, P = product_case
     C0, st0 = multiply(H, t, A, B, eps)
-    feats, ranks = H.hmat_product_features(C0)
     H.hmat_destroy(C0)
+    feats, widths = [], []
+    for pts in (jitter(fibonacci_sphere(4096), 1e-3, seed=9), ellipsoid(4096, (1.0, 0.7, 0.5))):
+        tt = H.hmat_build_tree(pts, 32, 0.8, 0)
+        At, _ = H.hmat_assemble(tt, "laplace_4pi", 1.0, 0.0, eps_in=1e-8)
+        Bt, _ = H.hmat_assemble(tt, "exp", 1.0, 1.0, eps_in=1e-8)
+        Ct, _ = multiply(H, tt, At, Bt, eps)
+        f, _ = H.hmat_product_features(Ct)
+        feats.append(f)
+        widths.append(H.hmat_product_widths(Ct))
+        for h in (At, Bt, Ct):
+            H.hmat_destroy(h)
+        H.hmat_tree_destroy(tt)
+    feats, widths = np.concatenate(feats), np.concatenate(widths)
     m = H.hmat_rank_model_create(1)
     try:
-        losses = H.hmat_rank_model_train(m, feats, ranks, H.hmat_train_opts_default(epochs=200, batch=128, lr=2e-3))
+        losses = H.hmat_rank_model_train(m, feats, widths, H.hmat_train_opts_default(epochs=200, batch=128, lr=2e-3))
         assert losses[-1] < losses[0]
         C1, st1 = multiply(H, t, A, B, eps, rank_mode=H.HMAT_RANK_PREDICT, rank_model=m)
         assert count_bad(H, t, C1, P, eps) == 0
         assert st1.n_not_converged == 0
-        print(f"eps {eps}: ranks {np.bincount(ranks.astype(int))}; plain: grown {st0.n_grown_blocks}, columns"
-              f" {st0.sketch_columns}, target passes {st0.target_passes}; learned: grown {st1.n_grown_blocks},"
-              f" columns {st1.sketch_columns}, fallback {st1.n_fallback}, target passes {st1.target_passes}",
-              flush=True)
+        print(f"eps {eps}: training widths {np.bincount(widths.astype(int))[8::8]} (8, 16, ...); plain: grown "
+              f"{st0.n_grown_blocks}, columns {st0.sketch_columns}, target passes {st0.target_passes}; learned: grown "
+              f"{st1.n_grown_blocks}, columns {st1.sketch_columns}, fallback {st1.n_fallback}, target passes "
+              f"{st1.target_passes}", flush=True)
         assert 0 <= st1.n_fallback <= st1.n_grown_blocks
+        assert st1.n_grown_blocks <= 0.5 * max(st0.n_grown_blocks, 1)
         if eps < 1e-7:
-            assert st1.n_grown_blocks < 0.5 * max(st0.n_grown_blocks, 1)
-            assert st1.target_passes < 0.9 * st0.target_passes
+            assert st1.target_passes < st0.target_passes
         else:
-            assert st1.target_passes <= 1.1 * st0.target_passes
+            assert st1.target_passes <= 1.05 * st0.target_passes
         H.hmat_destroy(C1)
     finally:
         H.hmat_rank_model_destroy(m)
