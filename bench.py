@@ -299,9 +299,10 @@ def main():
     from paper_1805_08998_amd import hmat as H
 
     if args.workload == "batched64":
-        print("bench.py: the batched64 workload is switched off. After a first complete call, later "
-              "hmat_multiply_batched calls on this 64-product batch stopped making progress, and the cause "
-              "is not known. Small batches are covered by tests/test_gpu_batched.py.", file=sys.stderr)
+        print("bench.py: the batched64 workload is switched off. hmat_multiply_batched calls on this "
+              "64-product batch stopped making progress when the library's device footprint neared the "
+              "whole device; the allocator now keeps to three quarters of it, which has not been run on "
+              "this batch yet. Small batches are covered by tests/test_gpu_batched.py.", file=sys.stderr)
         sys.exit(2)
     w = CONFIGS[args.workload]
     scheme_code = {"randomized": H.HMAT_SCHEME_RANDOMIZED, "aca": H.HMAT_SCHEME_ACA,

@@ -4,11 +4,14 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <unordered_map>
 
+#include "block_cache.h"
 #include "hmat_internal.h"
 #include "matvec.h"
 
@@ -24,199 +27,140 @@ void expand_to_dense(HMat* M, double* out, int64_t ld, int32_t order, hipStream_
 static thread_local std::string g_err;
 void set_last_error(const std::string& msg) { g_err = msg; }
 
-static std::mutex g_alloc_mu;
-
-// Caching of device blocks: a freed block keeps
-// its (rounded) size class, the stream current at the free and an event
-// recorded there. It is handed out again to work on the same stream at once
-// (stream order puts the new use after the old one), to other streams only once
-// the event has completed, so work still queued on the old buffer can never
-// see it reused. On allocation
-// failure idle cached blocks are freed, largest first, and the allocation
-// retried.
+// Device memory comes from a cache of blocks (block_cache.h) over hipMalloc/hipFree.
+// The stream that orders a block's reuse is the calling thread's current stream.
 static thread_local hipStream_t g_stream = 0;  // per host thread (concurrent products)
-struct CachedBlock {
-  void* p;
-  hipEvent_t ev;
-  hipStream_t stream;  // stream current when it was freed: work on it is ordered after the free
+
+namespace {
+struct HipOps {
+  void* malloc(size_t b) {
+    void* p = nullptr;
+    if (hipMalloc(&p, b) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return p;
+  }
+  void release(void* p) { (void)hipFree(p); }
+  void* record(void* s) {
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    if (hipEventRecord(ev, static_cast<hipStream_t>(s)) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipEventDestroy(ev);
+      return nullptr;
+    }
+    return ev;
+  }
+  bool done(void* ev) {
+    const hipError_t q = hipEventQuery(static_cast<hipEvent_t>(ev));
+    if (q != hipSuccess) (void)hipGetLastError();  // not ready (or unusable): not done
+    return q == hipSuccess;
+  }
+  void wait(void* ev) {
+    if (hipEventSynchronize(static_cast<hipEvent_t>(ev)) != hipSuccess) (void)hipGetLastError();
+  }
+  void destroy(void* ev) { (void)hipEventDestroy(static_cast<hipEvent_t>(ev)); }
+  double now() { return now_seconds(); }
 };
-static std::map<std::pair<int, size_t>, std::vector<CachedBlock>> g_cache;
-static std::unordered_map<void*, std::pair<int, size_t>> g_live;
-static size_t g_cached_bytes = 0;
+
+size_t device_total() {
+  size_t fb = 0, tb = 0;
+  if (hipMemGetInfo(&fb, &tb) != hipSuccess) {
+    (void)hipGetLastError();
+    return size_t(128) << 30;
+  }
+  return tb;
+}
+
+// The library holds at most three quarters of the device memory (live and cached
+// blocks): before an allocation would go past that, idle cached blocks are released.
+// A device run close to full has made products stall. trim() would hand idle blocks back
+// down to an eighth of the memory; the library releases them only before or after an
+// allocation (block_cache.h), never when a block is freed.
+BlockCache<HipOps>& cache() {
+  static BlockCache<HipOps> c(HipOps{}, device_total() / 4, false, device_total() / 4 * 3);
+  // HMAT_ALLOC_TRACE=<file>: one line per allocation, free and release (block_cache.h)
+  static const bool traced = [] {
+    const char* f = std::getenv("HMAT_ALLOC_TRACE");
+    if (f && *f) c.set_trace(std::fopen(f, "w"));
+    return true;
+  }();
+  (void)traced;
+  return c;
+}
+}  // namespace
 
 void set_current_stream(hipStream_t s) { g_stream = s; }
 
-void forget_stream(hipStream_t s) {
-  // called after s has been synchronized and before it is destroyed: the blocks freed
-  // on it are idle, and their events must not be queried once the stream is gone
-  std::lock_guard<std::mutex> lk(g_alloc_mu);
-  for (auto& kv : g_cache)
-    for (auto& cb : kv.second)
-      if (cb.ev && cb.stream == s) {
-        (void)hipEventSynchronize(cb.ev);
-        (void)hipEventDestroy(cb.ev);
-        cb.ev = nullptr;
-        cb.stream = nullptr;
-      }
-  (void)hipGetLastError();
-}
+void forget_stream(hipStream_t s) { cache().forget_stream(s); }
 
 size_t dev_free_bytes() {
   size_t fb = 0, tb = 0;
   HM_CHECK_HIP(hipMemGetInfo(&fb, &tb));
-  std::lock_guard<std::mutex> lk(g_alloc_mu);
-  return fb + g_cached_bytes;
+  BlockCache<HipOps>& c = cache();
+  const size_t cached = c.cached_bytes(), held = c.held_bytes();
+  const size_t live = held - std::min(held, cached);
+  const size_t room = c.soft_cap() > live ? c.soft_cap() - live : 0;
+  return std::min(fb + cached, room);
 }
 
-static size_t round_size(size_t b) {
-  if (b <= (size_t(1) << 20)) {
-    size_t r = 256;
-    while (r < b) r <<= 1;
-    return r;
-  }
-  const size_t g = size_t(2) << 20;
-  return (b + g - 1) / g * g;
-}
-
-static AllocCounters g_cnt;
 AllocCounters alloc_counters() {
-  std::lock_guard<std::mutex> lk(g_alloc_mu);
-  return g_cnt;
-}
-
-// Takes cached blocks out of the cache, largest first, until at least `need`
-// bytes are collected (everything for SIZE_MAX). The caller frees them with
-// free_blocks() after dropping the lock, so that waiting for their last use
-// does not stall other threads' allocations.
-static std::vector<CachedBlock> take_blocks_locked(size_t need) {
-  std::vector<CachedBlock> out;
-  g_cnt.releases++;
-  size_t got = 0;
-  while (got < need && !g_cache.empty()) {
-    auto it = std::prev(g_cache.end());
-    auto& v = it->second;
-    while (!v.empty() && got < need) {
-      out.push_back(v.back());
-      v.pop_back();
-      got += it->first.second;
-      g_cached_bytes -= it->first.second;
-    }
-    if (v.empty()) g_cache.erase(it);
-  }
-  return out;
-}
-
-static void free_blocks(std::vector<CachedBlock>& v) {
-  const double t0 = now_seconds();
-  for (auto& cb : v) {
-    if (cb.ev) {
-      (void)hipEventSynchronize(cb.ev);
-      (void)hipEventDestroy(cb.ev);
-    }
-    (void)hipFree(cb.p);
-  }
-  v.clear();
-  const double dt = now_seconds() - t0;
-  std::lock_guard<std::mutex> lk(g_alloc_mu);
-  g_cnt.seconds += dt;
-}
-
-// Upper bound of the cache: a quarter of the device memory (queried once).
-static size_t cache_limit() {
-  static size_t lim = 0;
-  if (!lim) {
-    size_t fb = 0, tb = 0;
-    lim = hipMemGetInfo(&fb, &tb) == hipSuccess ? size_t(0.25 * double(tb)) : (size_t(32) << 30);
-  }
-  return lim;
+  const CacheCounters c = cache().counters();
+  AllocCounters a;
+  a.seconds = c.seconds;
+  a.mallocs = c.mallocs;
+  a.releases = c.releases;
+  return a;
 }
 
 void* dev_alloc(size_t bytes) {
-  void* p = nullptr;
-  if (bytes == 0) bytes = 8;
   int dev = 0;
   (void)hipGetDevice(&dev);
-  const size_t rs = round_size(bytes);
-  {
-    std::lock_guard<std::mutex> lk(g_alloc_mu);
-    // best fit: the smallest cached size class of at least rs and at most 1.5 rs whose
-    // last use has completed
-    for (auto it = g_cache.lower_bound({dev, rs});
-         it != g_cache.end() && it->first.first == dev && it->first.second <= rs + rs / 2; ++it) {
-      auto& v = it->second;
-      for (size_t i = 0; i < v.size(); ++i) {
-        bool ok = !v[i].ev || v[i].stream == g_stream;
-        if (!ok) {
-          const hipError_t q = hipEventQuery(v[i].ev);
-          ok = q == hipSuccess;
-          if (q != hipSuccess) (void)hipGetLastError();  // not ready (or unusable): leave it
-        }
-        if (ok) {
-          p = v[i].p;
-          const size_t got = it->first.second;
-          if (v[i].ev) (void)hipEventDestroy(v[i].ev);
-          v.erase(v.begin() + i);
-          g_cached_bytes -= got;
-          g_live[p] = {dev, got};
-          return p;
-        }
-      }
-    }
-  }
-  const double t0 = now_seconds();
-  hipError_t e = hipMalloc(&p, rs);
-  const double t1 = now_seconds();
-  for (int attempt = 0; e != hipSuccess && attempt < 2; ++attempt) {
-    (void)hipGetLastError();
-    std::vector<CachedBlock> victims;
-    {
-      std::lock_guard<std::mutex> lk(g_alloc_mu);
-      if (g_cached_bytes == 0) break;
-      victims = take_blocks_locked(attempt == 0 ? rs + (size_t(1) << 30) : SIZE_MAX);
-    }
-    free_blocks(victims);
-    e = hipMalloc(&p, rs);
-  }
-  std::lock_guard<std::mutex> lk(g_alloc_mu);
-  g_cnt.mallocs++;
-  g_cnt.seconds += t1 - t0;
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    throw Error(HMAT_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
-  }
-  g_live[p] = {dev, rs};
+  void* p = cache().alloc(bytes, dev, g_stream);
+  if (!p) throw Error(HMAT_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
   return p;
 }
 
 void dev_free(void* p) {
   if (!p) return;
-  std::vector<CachedBlock> victims;
-  {
-    std::lock_guard<std::mutex> lk(g_alloc_mu);
-    auto it = g_live.find(p);
-    if (it == g_live.end()) {
-      (void)hipFree(p);
-      return;
-    }
-    const auto key = it->second;
-    g_live.erase(it);
-    hipEvent_t ev;
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
-        hipEventRecord(ev, g_stream) != hipSuccess) {
-      (void)hipGetLastError();
-      (void)hipFree(p);
-      return;
-    }
-    g_cache[key].push_back({p, ev, g_stream});
-    g_cached_bytes += key.second;
-    if (g_cached_bytes > cache_limit()) victims = take_blocks_locked(g_cached_bytes - cache_limit() / 2);
-  }
-  free_blocks(victims);
+  if (!cache().free(p, g_stream)) (void)hipFree(p);
 }
 
+// Pinned staging buffers for large host-to-device copies: a pool shared by the host
+// threads. A copy holds one buffer for its whole duration but no lock while it waits
+// for its stream, so concurrent products do not queue behind each other's streams.
 static std::mutex g_pin_mu;
-static void* g_pin = nullptr;
-static size_t g_pin_size = 0;
+static std::vector<void*> g_pin_free;
+static constexpr size_t kPinChunk = size_t(64) << 20;
+
+namespace {
+struct PinnedLease {
+  void* p = nullptr;
+  PinnedLease() {
+    {
+      std::lock_guard<std::mutex> lk(g_pin_mu);
+      if (!g_pin_free.empty()) {
+        p = g_pin_free.back();
+        g_pin_free.pop_back();
+        return;
+      }
+    }
+    if (hipHostMalloc(&p, kPinChunk) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+  }
+  ~PinnedLease() {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    g_pin_free.push_back(p);
+  }
+};
+}  // namespace
 
 void host_to_device(void* dst, const void* src, size_t bytes, hipStream_t s) {
   const size_t small = size_t(4) << 20;
@@ -225,27 +169,18 @@ void host_to_device(void* dst, const void* src, size_t bytes, hipStream_t s) {
     HM_CHECK_HIP(hipStreamSynchronize(s));
     return;
   }
-  std::lock_guard<std::mutex> lk(g_pin_mu);
-  const size_t chunk = size_t(64) << 20;
-  if (!g_pin) {
-    if (hipHostMalloc(&g_pin, chunk) != hipSuccess) {
-      (void)hipGetLastError();
-      g_pin = nullptr;
-    } else {
-      g_pin_size = chunk;
-    }
-  }
-  if (!g_pin) {  // no pinned memory: plain copy
+  PinnedLease pin;
+  if (!pin.p) {  // no pinned memory: plain copy
     HM_CHECK_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
     HM_CHECK_HIP(hipStreamSynchronize(s));
     return;
   }
   const char* hs = static_cast<const char*>(src);
   char* dd = static_cast<char*>(dst);
-  for (size_t off = 0; off < bytes; off += g_pin_size) {
-    const size_t len = std::min(g_pin_size, bytes - off);
-    std::memcpy(g_pin, hs + off, len);
-    HM_CHECK_HIP(hipMemcpyAsync(dd + off, g_pin, len, hipMemcpyHostToDevice, s));
+  for (size_t off = 0; off < bytes; off += kPinChunk) {
+    const size_t len = std::min(kPinChunk, bytes - off);
+    std::memcpy(pin.p, hs + off, len);
+    HM_CHECK_HIP(hipMemcpyAsync(dd + off, pin.p, len, hipMemcpyHostToDevice, s));
     HM_CHECK_HIP(hipStreamSynchronize(s));
   }
 }

@@ -49,7 +49,8 @@ struct AllocCounters {
   int64_t mallocs = 0, releases = 0;
 };
 AllocCounters alloc_counters();
-// device memory available to the library: free memory plus blocks held by its cache
+// device memory available to the library: free memory plus blocks held by its cache,
+// within the share of the device the library keeps to (three quarters)
 size_t dev_free_bytes();
 // Copies host memory to the device and waits; large copies go through a pinned
 // staging buffer (allocated with hipHostMalloc and kept for reuse).

@@ -105,17 +105,22 @@ def test_batched_empty(H):
     assert Cs == [] and list(status) == []
 
 
-BATCH64_SKIP = ("batch of 64 products (4096 to 65536 points): a second call on this batch stopped making "
-                "progress on the GPU, and the cause is not shown; the case stays off the GPU until it is")
+BATCH64_SKIP = ("batch of 64 products (4096 to 65536 points): calls stopped making progress on the GPU, the "
+                "second call under the allocator's first policy and the first call under its second; the "
+                "simulated footprint of exactly those calls nears the whole device (tests/test_alloc_cache.py). "
+                "The allocator now keeps to three quarters of the device; that is not yet run on this batch")
 
 
+@pytest.mark.slow
 @pytest.mark.skip(reason=BATCH64_SKIP)
 def test_batched64_two_calls(H):
     """The 64-product workload (n log-uniform in [4096, 65536], random geometries and
     kernel pairs), called twice: both calls complete, and every product of the
     second call equals the first (plain mode is deterministic)."""
+    import time
     from workloads import batched_geometries
     specs = batched_geometries(64, seed=0)
+    print("[batched64] building 64 trees and 128 matrices", flush=True)
     trees, As, Bs = [], [], []
     for sp in specs:
         t = H.hmat_build_tree(sp["points"], 64, 0.8, 0)
@@ -123,8 +128,12 @@ def test_batched64_two_calls(H):
         B, _ = H.hmat_assemble(t, sp["kernel_b"], 1.0, 0.0, eps_in=1e-8)
         trees.append(t), As.append(A), Bs.append(B)
     o = H.hmat_opts_default()
+    t0 = time.monotonic()
     C1, s1 = H.hmat_multiply_batched(As, Bs, 1e-6, o)
+    t1 = time.monotonic()
+    print(f"[batched64] first call {t1 - t0:.1f} s", flush=True)
     C2, s2 = H.hmat_multiply_batched(As, Bs, 1e-6, o)
+    print(f"[batched64] second call {time.monotonic() - t1:.1f} s", flush=True)
     assert list(s1) == [0] * 64 and list(s2) == [0] * 64
     for a, b in zip(C1, C2):
         assert all(np.array_equal(x, y) for x, y in zip(pool_of(H, a), pool_of(H, b)))
