@@ -219,7 +219,7 @@ typedef struct {
   int32_t precision;   /* HMAT_FP64 (default) or HMAT_FP32_APPLY */
   int32_t rank_mode;   /* HMAT_RANK_ADAPTIVE (default) or HMAT_RANK_PREDICT: the model's output
                           per farfield block is read as the sketch width the block needs; a
-                          prediction up to b0 + growth / 2 keeps the first width b0, above it the
+                          prediction up to b0 + 3 growth / 4 keeps the first width b0, above it the
                           first width is the prediction plus p_l (rounded up to the 16-column
                           pass granularity) */
   int32_t b0;          /* initial sketch width (default 8) */

@@ -13,6 +13,7 @@
 //    by applying their sum-expression to the identity.
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <cstring>
 #include <future>
 #include <map>
@@ -1885,7 +1886,7 @@ void evaluate_chunk(Ctx& c, Chunk& ch, double* cpool, const std::vector<int64_t>
   const Tree& t = *c.t;
   const int nt = int(ch.blocks.size());
   // direct kernel: terms and dense x dense pairs of the targets of at most NEAR_MAX x NEAR_MAX,
-  // one work item per 64 x 64 sub-block
+  // one work item per 64-row block (the kernel takes its column blocks in turn)
   std::vector<int32_t> dblk, items;
   std::vector<int64_t> dco;
   for (int i = 0; i < nt; ++i) {
@@ -1893,11 +1894,10 @@ void evaluate_chunk(Ctx& c, Chunk& ch, double* cpool, const std::vector<int64_t>
     const int32_t b = ch.blocks[i];
     const int m = c.m_of(b), n = c.n_of(b);
     const int k = int32_t(dblk.size());
-    for (int rb = 0; rb < (m + 63) / 64; ++rb)
-      for (int cb = 0; cb < (n + 63) / 64; ++cb) {
-        items.push_back(k);
-        items.push_back((rb << 16) | cb);
-      }
+    for (int rb = 0; rb < (m + 63) / 64; ++rb) {
+      items.push_back(k);
+      items.push_back(rb << 16);
+    }
     double by = 8.0 * m * n, fl = 0.0;
     for (int32_t a = b; a >= 0; a = t.b_parent[a])
       for (int32_t j = c.group_ptr_h[a]; j < c.group_ptr_h[a + 1]; ++j) {
@@ -2123,6 +2123,37 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   for (int32_t b : t->leaves) (t->b_kind[b] == KIND_F ? far_all : near_all).push_back(b);
   c.st.n_far = int64_t(far_all.size());
   c.st.n_near = int64_t(near_all.size());
+  // Learned mode: one prediction per farfield target, made before the targets are put
+  // into chunks. The prediction estimates the sketch width a target needs. A target is
+  // widened only where the prediction is well into the first growth step: a chunk's
+  // operator passes run as long as its widest target needs them, so a widened target that
+  // did not need it costs its chunk a pass, while one that did saves only the growth
+  // round's check and synchronisation (its extra pass is paid either way).
+  std::vector<float> pred_of;  // per block
+  const double widen_at = opts.o.b0 + 0.75 * opts.o.growth;
+  if (predict && !far_all.empty()) {
+    const double tq = now_seconds();
+    std::vector<float> fe(far_all.size() * size_t(HMAT_N_FEATURES));
+    {
+      const size_t nthr = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+      std::vector<std::thread> th;
+      for (size_t w = 0; w < nthr; ++w)
+        th.emplace_back([&, w] {
+          for (size_t i = w; i < far_all.size(); i += nthr)
+            target_features(c, far_all[i], &fe[i * HMAT_N_FEATURES]);
+        });
+      for (auto& x : th) x.join();
+    }
+    std::vector<float> pv;
+    predict_ranks(opts.o.rank_model, fe, pv, s);
+    pred_of.assign(size_t(nb), std::numeric_limits<float>::quiet_NaN());
+    for (size_t i = 0; i < far_all.size(); ++i) pred_of[far_all[i]] = pv[i];
+    c.st.t_predict += now_seconds() - tq;
+  }
+  auto predicted_wide = [&](int32_t b) {
+    const float pv = pred_of[b];
+    return std::isfinite(pv) && double(pv) > widen_at;
+  };
   int64_t near_len = 0;
   std::vector<int64_t> near_off(nb, -1);
   for (int32_t b : near_all) {
@@ -2232,7 +2263,7 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     ch->blocks = job.blocks;
     ch->near = !job.far;
     ch->share_s1 = !(job.far && own_inputs);
-    const bool features = job.far && (predict || collect);
+    const bool features = job.far && collect;
     if (overlap) {
       next = std::async(std::launch::async, build, std::move(ch), features);
     } else {
@@ -2263,29 +2294,24 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
       } else {
         std::vector<int32_t> w0(ch.blocks.size(), opts.o.b0);
         if (predict) {
-          // learned initial widths: the prediction estimates the sketch width a block needs
-          // (the residual check still grows the sketch where it is too small)
-          const double tq = now_seconds();
-          std::vector<float> pred;
-          predict_ranks(opts.o.rank_model, ch.feats, pred, s);
+          // learned initial widths (the residual check still grows the sketch where the
+          // prediction is too small)
           for (size_t i = 0; i < w0.size(); ++i) {
             const int mn = std::min(c.m_of(ch.blocks[i]), c.n_of(ch.blocks[i]));
-            const double pv = std::isfinite(pred[i]) ? double(pred[i]) : double(opts.o.b0);
+            const double pv = double(pred_of[ch.blocks[i]]);
             const int g = opts.o.probes;
-            // a prediction below the middle of the first growth step keeps the plain initial
-            // width (its first pass most likely suffices; a regression trained mostly on
-            // blocks of that width scatters around it); above, the width is the prediction
-            // plus p_l
-            const double widen_at = opts.o.b0 + 0.5 * opts.o.growth;
-            int w = pv <= widen_at ? opts.o.b0
-                                   : int(std::clamp(std::ceil(pv) + opts.o.p_l, 1.0, double(64 - g)));
+            // a prediction below three quarters of the first growth step keeps the plain
+            // initial width (a regression trained mostly on blocks of that width scatters
+            // around it); above, the width is the prediction plus p_l
+            int w = !predicted_wide(ch.blocks[i])
+                        ? opts.o.b0
+                        : int(std::clamp(std::ceil(pv) + opts.o.p_l, 1.0, double(64 - g)));
             // operator passes run PW columns at a time: widen the sketch as far as it
             // costs no extra pass of the sketch (w + g columns) or of the projection (w)
             const int up_s = (w + g + PW - 1) / PW * PW - g, up_p = (w + PW - 1) / PW * PW;
             w = std::min({up_s, up_p, 64 - g});
             w0[i] = int32_t(std::max(1, std::min(w, mn)));
           }
-          c.st.t_predict += now_seconds() - tq;
         }
         outs.emplace_back();
         if (jobs[k].exact) compress_chunk_exact(c, ch, outs.back());

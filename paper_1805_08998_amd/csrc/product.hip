@@ -889,42 +889,39 @@ namespace hm {
 // evaluated directly (S applied to the identity, the nearfield step of
 // Algorithm 4, without forming S I column block by column block). Pairs with a
 // subdivided factor are added afterwards through identity panels. One
-// workgroup per 64 x 64 sub-block (item = target, row block, column block);
-// wave q owns columns [16q, 16q + 16) of it, so every term panel is read once
-// per sub-block instead of once per 16 columns.
-// Every term of a direct target has kl, kr <= NEAR_TERM_MAX (the host routes other targets
-// to the identity panels), so a term's L rows and core fit the LDS tiles.
-// The four waves of a workgroup share one 64-row sub-block: the tiles every wave reads
-// (a term's L rows and core, a dense pair's A rows) are staged once in LDS by all 256
-// threads, then each wave multiplies them with its own 16 columns. Waves without columns
-// (narrow targets) still help stage the tiles and reach every barrier, so the loops below
-// are uniform across the workgroup.
-constexpr int NEAR_LD = 64;  // leading dimension of the LDS tiles (rows of the sub-block)
-
+// workgroup per 64-row block of a target (item = target, row block), which takes
+// the target's 64-column blocks in turn; wave q owns columns [16q, 16q + 16) of
+// each, so every term panel is read once per 64 x 64 sub-block instead of once
+// per 16 columns, and from L2 after the first column block. Every term of a direct target has
+// kl, kr <= NEAR_TERM_MAX (the host routes other targets to the identity panels), so
+// V below holds a whole term.
 __global__ void __launch_bounds__(256) k_near_direct(const int32_t* __restrict__ items,
                                                     const int32_t* __restrict__ blocks,
                                                     const int64_t* __restrict__ coff,
                                                     const int32_t* __restrict__ pptr,
                                                     const int32_t* __restrict__ pairs, TreeView tv, MatView ma,
                                                     MatView mb, double* __restrict__ cpool) {
-  __shared__ double tile_l[NEAR_LD * 64];  // L rows of the sub-block (64 x kl), or A rows (64 x nr)
-  __shared__ double tile_c[64 * 64];       // core (kl x kr)
   const int t = items[2 * blockIdx.x], rc = items[2 * blockIdx.x + 1];
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
   const int tb = blocks[t];
   const int tau = tv.b_tau[tb], sig = tv.b_sigma[tb];
   const int mt = tv.c_size[tau], nt = tv.c_size[sig];
-  const int rb0 = 64 * (rc >> 16), cb0 = 64 * (rc & 0xffff);  // sub-block origin
-  const int m = min(64, mt - rb0);                               // rows of this sub-block
+  const int rb0 = 64 * (rc >> 16);   // row block origin
+  const int m = min(64, mt - rb0);   // rows of this row block
   const int n = nt;
-  const int col0 = cb0 + 16 * wid;
-  const bool wave_on = col0 < min(n, cb0 + 64);  // this wave has output columns
   const int out0 = tv.c_begin[tau] + rb0, in0 = tv.c_begin[sig];
+  // the column blocks of the row block one after the other: the term panels and A rows
+  // this workgroup reads for the first come from L2 for the others
+  for (int cb0 = 0; cb0 < n; cb0 += 64) {
+  const int col0 = cb0 + 16 * wid;
+  if (col0 >= min(n, cb0 + 64)) break;  // no columns for this wave here or further right; no barriers follow
   const int ntile = (m + 15) >> 4;
   const int jc = col0 + li;  // column of this lane in B operands and in the output
-  const bool jok = wave_on && jc < n && jc < cb0 + 64;
-  const int jcl = max(0, min(jc, min(n, cb0 + 64) - 1));  // clamped: every lane loads in bounds
+  const bool jok = jc < n && jc < cb0 + 64;
+  const int jcl = min(jc, min(n, cb0 + 64) - 1);  // clamped: every lane loads in bounds
+  // All loads below come from clamped in-bounds addresses and are masked, so the MFMA
+  // chains run without branches and the loads of a group are in flight together.
   dbl4 y[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) y[q] = dbl4{0.0, 0.0, 0.0, 0.0};
@@ -932,114 +929,97 @@ __global__ void __launch_bounds__(256) k_near_direct(const int32_t* __restrict__
     for (int it = tv.group_ptr[a]; it < tv.group_ptr[a + 1]; ++it) {
       const Term T = tv.terms[it];
       const int kl = T.kl, kr = T.kr;
-      const int64_t lr = int64_t(out0 - T.lrow0);
-      // stage L rows (rows past m repeat row m - 1: masked below) and the core
-      for (int e = threadIdx.x; e < 64 * kl; e += 256) {
-        const int r = e & 63, c = e >> 6;
-        tile_l[r + NEAR_LD * c] = T.L[(lr + min(r, m - 1)) + int64_t(c) * T.ldl];
-      }
-      if (T.core)
-        for (int e = threadIdx.x; e < kl * kr; e += 256) tile_c[e] = T.core[e];
-      __syncthreads();
-      if (wave_on) {
-        const int64_t rrow = int64_t(in0 + jcl - T.rrow0);  // R row of this lane's column
-        const int rt = T.rtrans;
-        // V = core R_slab^T (kl x 16) in accumulator layout: V[ob][v] = V(16 ob + lk + 4 v, li)
-        const int nob = (kl + 15) >> 4;
-        dbl4 V[4];
-        if (T.core) {
-          const int ks = (kr + 3) >> 2;
+      const int64_t rrow = int64_t(in0 + jcl - T.rrow0);  // R row of this lane's column
+      const int rt = T.rtrans;
+      // V = core R_slab^T (kl x 16) in accumulator layout: V[ob][v] = V(16 ob + lk + 4 v, li)
+      const int nob = (kl + 15) >> 4;
+      dbl4 V[4];
+      if (T.core) {
+        const int ks = (kr + 3) >> 2;
 #pragma unroll
-          for (int ob = 0; ob < 4; ++ob) {
-            V[ob] = dbl4{0.0, 0.0, 0.0, 0.0};
-            if (ob < nob) {
-              const int i = 16 * ob + li;
-              const int icl = min(i, kl - 1);
-              for (int s0 = 0; s0 < ks; s0 += 4) {
-                double av[4], bv[4];
+        for (int ob = 0; ob < 4; ++ob) {
+          V[ob] = dbl4{0.0, 0.0, 0.0, 0.0};
+          if (ob < nob) {
+            const int i = 16 * ob + li;
+            const int icl = min(i, kl - 1);
+            for (int s0 = 0; s0 < ks; s0 += 4) {
+              double av[4], bv[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                  const int ccl = min(4 * (s0 + q) + lk, kr - 1);
-                  av[q] = tile_c[icl + ccl * kl];
-                  bv[q] = rt ? T.R[ccl + rrow * T.ldr] : T.R[rrow + int64_t(ccl) * T.ldr];
-                }
+              for (int q = 0; q < 4; ++q) {
+                const int ccl = min(4 * (s0 + q) + lk, kr - 1);
+                av[q] = T.core[icl + int64_t(ccl) * kl];
+                bv[q] = rt ? T.R[ccl + rrow * T.ldr] : T.R[rrow + int64_t(ccl) * T.ldr];
+              }
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                  const int cc = 4 * (s0 + q) + lk;
-                  V[ob] = mfma4(masked(i < kl && cc < kr, av[q]), masked(cc < kr && jok, bv[q]), V[ob]);
-                }
+              for (int q = 0; q < 4; ++q) {
+                const int cc = 4 * (s0 + q) + lk;
+                V[ob] = mfma4(masked(i < kl && cc < kr, av[q]), masked(cc < kr && jok, bv[q]), V[ob]);
               }
             }
           }
-        } else {
-#pragma unroll
-          for (int ob = 0; ob < 4; ++ob) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int cc = 16 * ob + lk + 4 * v;
-              const int ccl = min(cc, kr - 1);
-              const double val = rt ? T.R[ccl + rrow * T.ldr] : T.R[rrow + int64_t(ccl) * T.ldr];
-              V[ob][v] = masked(ob < nob && cc < kr && jok, val);
-            }
-          }
         }
-        // y += L_tau V: all four row tiles, rows past m masked
+      } else {
 #pragma unroll
         for (int ob = 0; ob < 4; ++ob) {
-          if (ob < nob) {
 #pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) {
-              const int cc = 16 * ob + 4 * s4 + lk;
-              const int ccl = min(cc, kl - 1);
-#pragma unroll
-              for (int tile = 0; tile < 4; ++tile)
-                y[tile] = mfma4(masked(cc < kl && 16 * tile + li < m, tile_l[16 * tile + li + NEAR_LD * ccl]),
-                                V[ob][s4], y[tile]);
-            }
+          for (int v = 0; v < 4; ++v) {
+            const int cc = 16 * ob + lk + 4 * v;
+            const int ccl = min(cc, kr - 1);
+            const double val = rt ? T.R[ccl + rrow * T.ldr] : T.R[rrow + int64_t(ccl) * T.ldr];
+            V[ob][v] = masked(ob < nob && cc < kr && jok, val);
           }
         }
       }
-      __syncthreads();  // the tiles are overwritten by the next term
+      // y += L_tau V: all four row tiles, rows past m masked
+      const int64_t lr = int64_t(out0 - T.lrow0);
+#pragma unroll
+      for (int ob = 0; ob < 4; ++ob) {
+        if (ob < nob) {
+          double av[4][4];
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const int ccl = min(16 * ob + 4 * s4 + lk, kl - 1);
+#pragma unroll
+            for (int tile = 0; tile < 4; ++tile)
+              av[s4][tile] = T.L[(lr + min(16 * tile + li, m - 1)) + int64_t(ccl) * T.ldl];
+          }
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const int cc = 16 * ob + 4 * s4 + lk;
+#pragma unroll
+            for (int tile = 0; tile < 4; ++tile)
+              y[tile] = mfma4(masked(cc < kl && 16 * tile + li < m, av[s4][tile]), V[ob][s4], y[tile]);
+          }
+        }
+      }
     }
   }
-  // dense pairs: y += A[tau, rho] B[rho, sigma][:, slab]; the A rows staged in LDS
+  // dense pairs: y += A[tau, rho] B[rho, sigma][:, slab], two K-steps per group
   for (int p = pptr[t]; p < pptr[t + 1]; ++p) {
     const int qa = pairs[2 * p], qb = pairs[2 * p + 1];
     const int nr = tv.c_size[tv.b_sigma[qa]];
     const double* Ab = ma.pool + ma.off[qa] + rb0;  // rows of this sub-block, leading dimension mt
     const double* Bb = mb.pool + mb.off[qb];        // nr x n, column-major
-    for (int k0 = 0; k0 < nr; k0 += 64) {           // 64 columns of A (rows of B) at a time
-      const int nk = min(64, nr - k0);
-      for (int e = threadIdx.x; e < 64 * nk; e += 256) {
-        const int r = e & 63, c = e >> 6;
-        tile_l[r + NEAR_LD * c] = Ab[min(r, m - 1) + int64_t(k0 + c) * mt];
+    const int ks = (nr + 3) >> 2;
+    for (int s0 = 0; s0 < ks; s0 += 2) {
+      double bv[2], av[2][4];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int ccl = min(4 * (s0 + q) + lk, nr - 1);
+        bv[q] = Bb[ccl + int64_t(jcl) * nr];
+#pragma unroll
+        for (int tile = 0; tile < 4; ++tile) av[q][tile] = Ab[min(16 * tile + li, m - 1) + int64_t(ccl) * mt];
       }
-      __syncthreads();
-      if (wave_on) {
-        const int ks = (nk + 3) >> 2;
-        for (int s0 = 0; s0 < ks; s0 += 2) {
-          double bv[2];
 #pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            const int ccl = min(4 * (s0 + q) + lk, nk - 1);
-            bv[q] = Bb[(k0 + ccl) + int64_t(jcl) * nr];
-          }
+      for (int q = 0; q < 2; ++q) {
+        const int cc = 4 * (s0 + q) + lk;
+        const double b = masked(cc < nr && jok, bv[q]);
 #pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            const int cc = 4 * (s0 + q) + lk;
-            const int ccl = min(cc, nk - 1);
-            const double b = masked(cc < nk && jok, bv[q]);
-#pragma unroll
-            for (int tile = 0; tile < 4; ++tile)
-              y[tile] = mfma4(masked(cc < nk && 16 * tile + li < m, tile_l[16 * tile + li + NEAR_LD * ccl]), b,
-                              y[tile]);
-          }
-        }
+        for (int tile = 0; tile < 4; ++tile)
+          y[tile] = mfma4(masked(cc < nr && 16 * tile + li < m, av[q][tile]), b, y[tile]);
       }
-      __syncthreads();
     }
   }
-  if (!wave_on) return;
   double* Cb = cpool + coff[t] + rb0;  // C block is mt x n, column-major
 #pragma unroll
   for (int tile = 0; tile < 4; ++tile) {
@@ -1048,6 +1028,7 @@ __global__ void __launch_bounds__(256) k_near_direct(const int32_t* __restrict__
       const int r = 16 * tile + lk + 4 * v;
       if (tile < ntile && r < m && jok) Cb[r + int64_t(jc) * mt] = y[tile][v];
     }
+  }
   }
 }
 

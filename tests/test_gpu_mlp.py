@@ -186,9 +186,12 @@ def test_learned_mode(H, product_case, eps):
     """The predictor is trained out of sample: on the sketch widths (hmat_product_widths)
     of a product on other points (another jitter draw of the sphere and the ellipsoid
     with axes 1, 0.7, 0.5), then applied to this product. The learned mode keeps every
-    block within the bound and grows at most half as many blocks as the plain form; at
-    eps = 1e-8, where most blocks grow, it also makes fewer operator passes (its wider
-    first sketches take passes of their own); at eps = 1e-6 at most 5 % more."""
+    block within the bound. At eps = 1e-8, where most blocks grow, it grows at most half
+    as many blocks as the plain form and makes fewer operator passes (its wider first
+    sketches take passes of their own). At eps = 1e-6 (ranks around 6, inside the plain
+    width) a block is widened only where the prediction is three quarters into the first
+    growth step: it grows at most three quarters as many blocks, with at most 5 % more
+    passes."""
     from workloads import ellipsoid
     t, A, B, P = product_case
     C0, st0 = multiply(H, t, A, B, eps)
@@ -218,10 +221,11 @@ def test_learned_mode(H, product_case, eps):
               f"{st1.n_grown_blocks}, columns {st1.sketch_columns}, fallback {st1.n_fallback}, target passes "
               f"{st1.target_passes}", flush=True)
         assert 0 <= st1.n_fallback <= st1.n_grown_blocks
-        assert st1.n_grown_blocks <= 0.5 * max(st0.n_grown_blocks, 1)
         if eps < 1e-7:
+            assert st1.n_grown_blocks <= 0.5 * max(st0.n_grown_blocks, 1)
             assert st1.target_passes < st0.target_passes
         else:
+            assert st1.n_grown_blocks <= 0.75 * max(st0.n_grown_blocks, 1)
             assert st1.target_passes <= 1.05 * st0.target_passes
         H.hmat_destroy(C1)
     finally:
