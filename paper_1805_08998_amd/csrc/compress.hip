@@ -191,34 +191,72 @@ __global__ void __launch_bounds__(NT) k_core(CTarget* __restrict__ tg, int nt, i
     if (threadIdx.x == 0) M[j * LD + j] = d;
     __syncthreads();
   }
-  // one-sided Jacobi on the columns of M (r x r), accumulating J; wave 0 only
+  // One-sided Jacobi on the columns of M (r x r), accumulating J; wave 0 only. The pairs
+  // are taken in parallel (round-robin) order: a sweep is nr - 1 rounds of nr / 2 disjoint
+  // pairs (nr = r rounded up to even; pairs with the padding index are skipped), and each
+  // pair is rotated by a group of G lanes at once. A group's rotation angle is taken from
+  // its first lane, so the lanes of a group apply the same rotation.
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     for (int i = 0; i < r; ++i)
       if (lane < r) J[i * LD + lane] = (lane == i) ? 1.0 : 0.0;
+    const int nr = (r + 1) & ~1;
+    int npair = 1;
+    while (npair < nr / 2) npair <<= 1;         // groups: a power of two, at most 32
+    const int G = 64 / npair;                   // lanes per group
+    const int grp = lane / G, gl = lane % G;    // group and lane within it
+    const int leader = grp * G;
     int capped = 1;
     for (int sweep = 0; sweep < 60; ++sweep) {
       int rotated = 0;
-      for (int p = 0; p < r - 1; ++p)
-        for (int q = p + 1; q < r; ++q) {
-          double mp = lane < r ? M[p * LD + lane] : 0.0;
-          double mq = lane < r ? M[q * LD + lane] : 0.0;
-          // one rotation for the whole wave: the angle must not differ between lanes
-          const double a = wave_uniform(wave_sum(mp * mp)), b = wave_uniform(wave_sum(mq * mq)),
-                       c = wave_uniform(wave_sum(mp * mq));
-          if (fabs(c) <= 1e-15 * sqrt(a * b) || c == 0.0) continue;
-          rotated = 1;
-          double zeta = (b - a) / (2.0 * c);
-          double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-          if (lane < r) {
-            M[p * LD + lane] = cs * mp - sn * mq;
-            M[q * LD + lane] = sn * mp + cs * mq;
-            double jp = J[p * LD + lane], jq = J[q * LD + lane];
-            J[p * LD + lane] = cs * jp - sn * jq;
-            J[q * LD + lane] = sn * jp + cs * jq;
+      for (int t = 0; t + 1 < nr; ++t) {
+        // round t of the circle schedule: position 0 holds index 0, position k >= 1 holds
+        // 1 + (k - 1 + t) mod (nr - 1); pair k joins positions k and nr - 1 - k
+        int p = -1, q = -1;
+        if (grp < nr / 2) {
+          const int k0 = grp, k1 = nr - 1 - grp;
+          const int i0 = k0 == 0 ? 0 : 1 + (k0 - 1 + t) % (nr - 1);
+          const int i1 = 1 + (k1 - 1 + t) % (nr - 1);
+          p = min(i0, i1);
+          q = max(i0, i1);
+        }
+        const bool live = p >= 0 && q < r;
+        double a = 0.0, b = 0.0, c = 0.0;
+        if (live)
+          for (int e = gl; e < r; e += G) {
+            const double mp = M[p * LD + e], mq = M[q * LD + e];
+            a += mp * mp;
+            b += mq * mq;
+            c += mp * mq;
+          }
+        for (int o = 1; o < G; o <<= 1) {  // within the group (G divides 64, groups aligned)
+          a += __shfl_xor(a, o, 64);
+          b += __shfl_xor(b, o, 64);
+          c += __shfl_xor(c, o, 64);
+        }
+        a = __shfl(a, leader, 64);
+        b = __shfl(b, leader, 64);
+        c = __shfl(c, leader, 64);
+        const bool rot = live && !(fabs(c) <= 1e-15 * sqrt(a * b) || c == 0.0);
+        if (rot) {
+          const double zeta = (b - a) / (2.0 * c);
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+          for (int e = gl; e < r; e += G) {
+            const double mp = M[p * LD + e], mq = M[q * LD + e];
+            M[p * LD + e] = cs * mp - sn * mq;
+            M[q * LD + e] = sn * mp + cs * mq;
+            const double jp = J[p * LD + e], jq = J[q * LD + e];
+            J[p * LD + e] = cs * jp - sn * jq;
+            J[q * LD + e] = sn * jp + cs * jq;
           }
         }
+        rotated |= __ballot(rot) != 0 ? 1 : 0;
+        // the next round reads columns other groups wrote: keep the LDS accesses in order
+        // (one wave: its LDS instructions complete in issue order)
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_wave_barrier();
+      }
       if (!rotated) {
         capped = 0;
         break;
