@@ -1,6 +1,6 @@
 """Benchmark of the H-matrix product C = A B on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sphere256k|...] [--mode learned|plain|mixed] [--eps E]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sphere256k|...] [--mode learned|plain|mixed|learned-mixed] [--eps E]
 
 One step is one whole product hmat_multiply(A, B, eps): every farfield block
 compressed, every nearfield block evaluated, on inputs already resident in HBM.
@@ -261,7 +261,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sphere256k")
-    ap.add_argument("--mode", default="learned", choices=["learned", "plain", "mixed"])
+    ap.add_argument("--mode", default="learned", choices=["learned", "plain", "mixed", "learned-mixed"],
+                    help="learned: predicted first widths; mixed: float32 sketch panels; learned-mixed: both")
     ap.add_argument("--train-on", default="sphere64k,ellipsoid256k",
                     help="workloads whose plain products provide the predictor's training data")
     ap.add_argument("--train-epochs", type=int, default=30)
@@ -315,7 +316,7 @@ def main():
         w = dataclasses.replace(w, eps=args.eps)
     model = None
     train_info = None
-    if args.mode == "learned":
+    if args.mode in ("learned", "learned-mixed"):
         model, train_info = train_predictor(H, CONFIGS, args.train_on.split(","), args.train_epochs,
                                             args.features_cache, eps=args.eps, target=args.train_target)
     pts = w.points()
@@ -333,9 +334,9 @@ def main():
     def run(time_kernels, mode=args.mode):
         st = H.hmat_stats()
         o = H.hmat_opts_default()
-        if mode == "mixed":
+        if mode in ("mixed", "learned-mixed"):
             o.precision = H.HMAT_FP32_APPLY
-        if mode == "learned":
+        if mode in ("learned", "learned-mixed"):
             o.rank_mode = H.HMAT_RANK_PREDICT
             o.rank_model = model
         o.time_kernels = 1 if time_kernels else 0
@@ -459,7 +460,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if args.mode == "mixed" else "f64",
+        "dtype": "f32+f64" if args.mode in ("mixed", "learned-mixed") else "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "geometry": w.geometry, "jitter": w.jitter, "leaf": w.leaf,
                    "eta": w.eta, "split": "midpoint" if w.split == 0 else "median",
