@@ -29,12 +29,12 @@
 
 namespace hm {
 
-void launch_leaf_reduce(const int64_t* pre, int ntask, int64_t nitems, const Task* tasks, const TDesc* td,
-                        const int32_t* dfs_block, const TreeView& tv, const MatView& ma, const MatView& mb,
-                        double* ws, hipStream_t s, bool lowp);
-void launch_subtree_expand(const int64_t* pre, int ntask, int64_t nitems, const Task* tasks, const TDesc* td,
+void launch_leaf_reduce(const int32_t* owner, int64_t nitems, const Task* tasks, const TDesc* td, const TreeView& tv,
+                        const MatView& ma, const MatView& mb, double* ws, hipStream_t s, bool lowp);
+void launch_subtree_expand(const int32_t* owner, int64_t nitems, const Task* tasks, const TDesc* td,
                            const TreeView& tv, const MatView& ma, const MatView& mb, const double* ws,
                            hipStream_t s, bool lowp);
+void launch_fill_owner(const int64_t* pre, int ntask, int32_t* owner, hipStream_t s);
 void launch_term_reduce(const TermItem* items, size_t n, const TDesc* td, const TInfo* ti, const TreeView& tv,
                         double* vbuf, hipStream_t s, bool lowp);
 void launch_gather_mfma(const RowItem* items, size_t n, const TDesc* td, const TInfo* ti, const HPair* hp,
@@ -121,9 +121,10 @@ void build_leaf_recs(const HMat* M, const DfsInfo& d, DevMat& dm, hipStream_t s)
     r.k = t.b_kind[b] == KIND_F ? M->rank[b] : -1;
     r.m = t.c_size[t.b_tau[b]];
     r.n = t.c_size[t.b_sigma[b]];
-    r.dfs = d.dfs_of_block[b];
+    r.kp = int32_t(dm.hkpref[d.dfs_of_block[b]]);
     return r;
   };
+  HM_REQUIRE(dm.hkpref.back() < int64_t(INT32_MAX), HMAT_ERR_ARG, "too many farfield ranks for 32-bit offsets");
   std::vector<LeafRec> rr(t.brow_blk.size()), cr(t.bcol_blk.size());
   for (size_t p = 0; p < rr.size(); ++p) rr[p] = rec(t.brow_blk[p], true);
   for (size_t p = 0; p < cr.size(); ++p) cr[p] = rec(t.bcol_blk[p], false);
@@ -233,7 +234,7 @@ struct Ctx {
   DevMat da, db;
   MatView ma, mb;
   TreeView tv;
-  DevBuf<int32_t> b_parent, b_dfs, group_ptr, d_dfs_block;
+  DevBuf<int32_t> b_parent, b_dfs, group_ptr;
   DevBuf<Term> terms;
   std::vector<SymTerm> sym;
   std::vector<int32_t> group_ptr_h;
@@ -488,6 +489,7 @@ struct TaskList {
   std::vector<int64_t> lpre{0}, rpre{0};
   DevBuf<Task> d_tasks;
   DevBuf<int64_t> d_lpre, d_rpre;
+  DevBuf<int32_t> d_lown, d_rown;  // per work item: (task, item within the task)
   int64_t ws_len = 0;
   void add(const Ctx& c, const Task& tk, bool expand) {
     const Tree& t = *c.t;
@@ -498,9 +500,16 @@ struct TaskList {
   }
   int ntask() const { return int(tasks.size()); }
   void upload(hipStream_t s) {
+    HM_REQUIRE(lpre.back() < int64_t(INT32_MAX) && rpre.back() < int64_t(INT32_MAX), HMAT_ERR_INTERNAL,
+               "too many subtree work items in one list");
     d_tasks.upload(tasks, s);
     d_lpre.upload(lpre, s);
     d_rpre.upload(rpre, s);
+    // the per-item tables are written on the device from the prefixes
+    d_lown.alloc(size_t(2 * std::max<int64_t>(lpre.back(), 1)));
+    d_rown.alloc(size_t(2 * std::max<int64_t>(rpre.back(), 1)));
+    launch_fill_owner(d_lpre.p, ntask(), d_lown.p, s);
+    launch_fill_owner(d_rpre.p, ntask(), d_rown.p, s);
   }
 };
 
@@ -574,13 +583,12 @@ void run_tasks(Ctx& c, TaskList& L, const TDesc* td, double* ws, bool expand, bo
   if (L.tasks.empty()) return;
   if (L.lpre.back() > 0) {
     c.timer.begin(K_LEAF);
-    launch_leaf_reduce(L.d_lpre.p, L.ntask(), L.lpre.back(), L.d_tasks.p, td, c.d_dfs_block.p, c.tv, c.ma, c.mb, ws,
-                       c.s, lowp);
+    launch_leaf_reduce(L.d_lown.p, L.lpre.back(), L.d_tasks.p, td, c.tv, c.ma, c.mb, ws, c.s, lowp);
     c.timer.end();
   }
   if (expand && L.rpre.back() > 0) {
     c.timer.begin(K_EXPAND);
-    launch_subtree_expand(L.d_rpre.p, L.ntask(), L.rpre.back(), L.d_tasks.p, td, c.tv, c.ma, c.mb, ws, c.s, lowp);
+    launch_subtree_expand(L.d_rown.p, L.rpre.back(), L.d_tasks.p, td, c.tv, c.ma, c.mb, ws, c.s, lowp);
     c.timer.end();
   }
 }
@@ -1155,6 +1163,7 @@ void upload_chunk(Chunk& ch, hipStream_t s) {
   ch.wsf.alloc(size_t(std::max<int64_t>(ch.tws_f, 1)));
   ch.wst.alloc(size_t(std::max<int64_t>(ch.tws_t, 1)));
   ch.d_td.alloc(ch.blocks.size() + ch.g_leaf.size());
+  HM_CHECK_HIP(hipStreamSynchronize(s));  // the work-item tables are written by kernels on s
 }
 
 // One application of every target's operator in the chunk (forward: S X, transposed: S^T X).
@@ -2033,7 +2042,6 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   }
   c.b_parent.upload(t->b_parent, s);
   c.b_dfs.upload(c.dfs.dfs_of_block, s);
-  c.d_dfs_block.upload(c.dfs.dfs_block, s);
   c.group_ptr.upload(c.group_ptr_h, s);
   c.hterms.swap(plan_arena().hterms);
   c.hterms.assign(c.sym.size(), Term{});

@@ -218,18 +218,10 @@ __global__ void __launch_bounds__(64) k_fused_terms(const int32_t* __restrict__ 
 }
 
 // ---------------------------------------------------------------- subtree products on MFMA
-// Work items are enumerated on the device: item g belongs to the task k with
-// pre[k] <= g < pre[k+1] (binary search), and is the (g - pre[k])-th depth-first
-// leaf of the task's subtree (reduction) or leaf cluster of its output (expansion).
-__device__ __forceinline__ int find_owner(const int64_t* __restrict__ pre, int n, int64_t g) {
-  int lo = 0, hi = n;  // pre[lo] <= g < pre[hi]
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (pre[mid] <= g) lo = mid;
-    else hi = mid;
-  }
-  return lo;
-}
+// Work items: item g belongs to the task k with pre[k] <= g < pre[k+1], and is the
+// (g - pre[k])-th depth-first leaf of the task's subtree (reduction) or leaf cluster of its
+// output (expansion). The subtree kernels read (k, g - pre[k]) from a table written on the
+// device when the task list is uploaded (one load instead of a search of dependent loads).
 
 // u = M[:, 16 kb : 16 kb + 16]^T X for one 16-column block of M (element (r, c) of the block
 // at r * msr + mcol, lane column c) and X's column li (Xg points at it). Groups of four
@@ -296,14 +288,13 @@ __device__ __forceinline__ void expand_dense(dbl4 (&y)[4], const __attribute__((
 }
 
 template <class TS>
-__global__ void __launch_bounds__(64) k_leaf_reduce(const int64_t* __restrict__ pre, int ntask, int64_t g0,
+__global__ void __launch_bounds__(64) k_leaf_reduce(const int32_t* __restrict__ owner, int64_t g0,
                                                    const Task* __restrict__ tasks, const TDesc* __restrict__ td,
-                                                   const int32_t* __restrict__ dfs_block, TreeView tv, MatView ma,
-                                                   MatView mb, double* __restrict__ ws) {
+                                                   TreeView tv, MatView ma, MatView mb, double* __restrict__ ws) {
   const int64_t g = g0 + blockIdx.x;
-  const int k = find_owner(pre, ntask, g);
+  const int k = owner[2 * g], item = owner[2 * g + 1];
   const Task tk = tasks[k];
-  const int dfs = tk.lo + int(g - pre[k]);
+  const int dfs = tk.lo + item;
   const MatView& mv = tk.mat ? mb : ma;
   const DfsRec L = mv.dfs_rec[dfs];
   const int kr = L.k;
@@ -351,12 +342,12 @@ __global__ void __launch_bounds__(64) k_leaf_reduce(const int64_t* __restrict__ 
 }
 
 template <class TS>
-__global__ void __launch_bounds__(64) k_subtree_expand(const int64_t* __restrict__ pre, int ntask, int64_t g0,
+__global__ void __launch_bounds__(64) k_subtree_expand(const int32_t* __restrict__ owner, int64_t g0,
                                                       const Task* __restrict__ tasks, const TDesc* __restrict__ td,
                                                       TreeView tv, MatView ma, MatView mb,
                                                       const double* __restrict__ ws) {
   const int64_t g = g0 + blockIdx.x;
-  const int kt = find_owner(pre, ntask, g);
+  const int kt = owner[2 * g], item = owner[2 * g + 1];
   const Task tk = tasks[kt];
   const double* X;
   int ldx, w, xident, xc0;
@@ -366,7 +357,7 @@ __global__ void __launch_bounds__(64) k_subtree_expand(const int64_t* __restrict
   const int qt = tv.b_tau[tk.q], qs = tv.b_sigma[tk.q];
   const int outc = tk.trans ? qs : qt, inc = tk.trans ? qt : qs;
   const int in0 = tv.c_begin[inc], in1 = in0 + tv.c_size[inc];
-  const int c = tv.leaf_clusters[tv.c_lc_begin[outc] + int(g - pre[kt])];
+  const int c = tv.leaf_clusters[tv.c_lc_begin[outc] + item];
   const int row_lo = tv.c_begin[c];
   const int nr = tv.c_size[c];  // leaf clusters have at most 64 rows
   const int ntile = (nr + 15) >> 4;
@@ -376,6 +367,7 @@ __global__ void __launch_bounds__(64) k_subtree_expand(const int64_t* __restrict
   for (int q = 0; q < 4; ++q) y[q] = dbl4{0.0, 0.0, 0.0, 0.0};
   const LeafRec* lst = tk.trans ? mv.col_rec : mv.row_rec;
   const int* lptr = tk.trans ? tv.bcol_ptr : tv.brow_ptr;
+  const int64_t kp_lo = mv.kpref[tk.lo];
   for (int a = c; a >= 0; a = tv.c_parent[a]) {
     int p0 = lptr[a];
     const int p1 = lptr[a + 1];
@@ -399,7 +391,7 @@ __global__ void __launch_bounds__(64) k_subtree_expand(const int64_t* __restrict
       if (L.k >= 0) {
         const int k = L.k;
         if (k == 0) continue;
-        const double* Tm = ws + tk.tws + (mv.kpref[L.dfs] - mv.kpref[tk.lo]) * PW;
+        const double* Tm = ws + tk.tws + (int64_t(L.kp) - kp_lo) * PW;
         const TS* P = tk.trans ? base + int64_t(k) * m : base;
         const int ldp = tk.trans ? n : m;
         const int ks = (k + 3) >> 2;
@@ -662,32 +654,48 @@ void launch_gather_mfma(const RowItem* items, size_t n, const TDesc* td, const T
   }
 }
 
-void launch_leaf_reduce(const int64_t* pre, int ntask, int64_t nitems, const Task* tasks, const TDesc* td,
-                        const int32_t* dfs_block, const TreeView& tv, const MatView& ma, const MatView& mb,
-                        double* ws, hipStream_t s, bool lowp) {
+// owner[2 g] = k and owner[2 g + 1] = g - pre[k] for pre[k] <= g < pre[k + 1]: one
+// workgroup per task
+__global__ void __launch_bounds__(64) k_fill_owner(const int64_t* __restrict__ pre, int ntask,
+                                                  int32_t* __restrict__ owner) {
+  const int k = blockIdx.x;
+  if (k >= ntask) return;
+  const int64_t g0 = pre[k], g1 = pre[k + 1];
+  for (int64_t g = g0 + threadIdx.x; g < g1; g += 64) {
+    owner[2 * g] = k;
+    owner[2 * g + 1] = int32_t(g - g0);
+  }
+}
+
+void launch_fill_owner(const int64_t* pre, int ntask, int32_t* owner, hipStream_t s) {
+  if (ntask <= 0) return;
+  hipLaunchKernelGGL(k_fill_owner, dim3(unsigned(ntask)), dim3(64), 0, s, pre, ntask, owner);
+  HM_CHECK_HIP(hipGetLastError());
+}
+
+void launch_leaf_reduce(const int32_t* owner, int64_t nitems, const Task* tasks, const TDesc* td, const TreeView& tv,
+                        const MatView& ma, const MatView& mb, double* ws, hipStream_t s, bool lowp) {
   const int64_t maxg = int64_t(1) << 30;
   for (int64_t b = 0; b < nitems; b += maxg) {
     unsigned cnt = unsigned(std::min(maxg, nitems - b));
     if (lowp)
-      hipLaunchKernelGGL(k_leaf_reduce<float>, dim3(cnt), dim3(64), 0, s, pre, ntask, b, tasks, td, dfs_block, tv, ma,
-                         mb, ws);
+      hipLaunchKernelGGL(k_leaf_reduce<float>, dim3(cnt), dim3(64), 0, s, owner, b, tasks, td, tv, ma, mb, ws);
     else
-      hipLaunchKernelGGL(k_leaf_reduce<double>, dim3(cnt), dim3(64), 0, s, pre, ntask, b, tasks, td, dfs_block, tv,
-                         ma, mb, ws);
+      hipLaunchKernelGGL(k_leaf_reduce<double>, dim3(cnt), dim3(64), 0, s, owner, b, tasks, td, tv, ma, mb, ws);
     HM_CHECK_HIP(hipGetLastError());
   }
 }
 
-void launch_subtree_expand(const int64_t* pre, int ntask, int64_t nitems, const Task* tasks, const TDesc* td,
+void launch_subtree_expand(const int32_t* owner, int64_t nitems, const Task* tasks, const TDesc* td,
                            const TreeView& tv, const MatView& ma, const MatView& mb, const double* ws,
                            hipStream_t s, bool lowp) {
   const int64_t maxg = int64_t(1) << 30;
   for (int64_t b = 0; b < nitems; b += maxg) {
     unsigned cnt = unsigned(std::min(maxg, nitems - b));
     if (lowp)
-      hipLaunchKernelGGL(k_subtree_expand<float>, dim3(cnt), dim3(64), 0, s, pre, ntask, b, tasks, td, tv, ma, mb, ws);
+      hipLaunchKernelGGL(k_subtree_expand<float>, dim3(cnt), dim3(64), 0, s, owner, b, tasks, td, tv, ma, mb, ws);
     else
-      hipLaunchKernelGGL(k_subtree_expand<double>, dim3(cnt), dim3(64), 0, s, pre, ntask, b, tasks, td, tv, ma, mb, ws);
+      hipLaunchKernelGGL(k_subtree_expand<double>, dim3(cnt), dim3(64), 0, s, owner, b, tasks, td, tv, ma, mb, ws);
     HM_CHECK_HIP(hipGetLastError());
   }
 }

@@ -33,7 +33,8 @@ struct LeafRec {
   int32_t o0, on;  // position and size of the other cluster (sigma in a row list, tau in a column list)
   int32_t k;       // farfield rank, -1 for a nearfield (dense) leaf
   int32_t m, n;    // rows and columns of the leaf
-  int32_t dfs;     // depth-first leaf index
+  int32_t kp;      // rank prefix of the leaf in depth-first order (kpref[dfs]): its leaf products'
+                   // offset in a subtree task's workspace, without a lookup
 };
 // The same, indexed by depth-first leaf index.
 struct DfsRec {
