@@ -415,6 +415,22 @@ hmat_status hmat_matvec_noalloc(hmat M, int32_t trans, int32_t order, int32_t nv
 hmat_status hmat_error_estimate(hmat C, hmat A, hmat B, const double* X0, int32_t p, int32_t iters, void* stream,
                                 double* err, double* norm_ab);
 
+/*
+ * The Gaussian test matrix Omega of the randomized scheme (Section 4.3): entry
+ * (i, j) is Box-Muller of one Philox4x32-10 block with counter (i mod 2^32, j,
+ * i div 2^32, 0x0A11CE5) and key (seed mod 2^32, seed div 2^32), output words
+ * w0..w3: a = (w0 2^21 xor w1 div 2^11) mod 2^53, b likewise from w2, w3,
+ * u1 = (a + 1) 2^-53, u2 = b 2^-53, Omega(i, j) = sqrt(-2 ln u1) cos(2 pi u2).
+ * Writes Omega(i, j) for i < n, j < ncol
+ * into DEVICE memory out (n x ncol, column-major, leading dimension n) on `stream`
+ * and returns when it is written. A product sketches the target block tau x sigma
+ * with the rows of sigma's positions (cluster order) of this matrix, seeded by
+ * opts.seed, so callers can reproduce its test vectors (for an error estimate on
+ * the same stream, or to check the generator).
+ * Errors: HMAT_ERR_ARG for a NULL out, negative sizes or n >= 2^38.
+ */
+hmat_status hmat_gaussian_panel(int64_t n, int32_t ncol, uint64_t seed, double* out, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Export                                                                   */
 /* ------------------------------------------------------------------------ */

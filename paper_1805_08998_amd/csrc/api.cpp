@@ -12,6 +12,7 @@
 #include <unordered_map>
 
 #include "block_cache.h"
+#include "compress.h"
 #include "hmat_internal.h"
 #include "matvec.h"
 
@@ -487,6 +488,16 @@ hmat_status hmat_error_estimate(hmat Ch, hmat Ah, hmat Bh, const double* X0, int
   HM_REQUIRE(A->tree->dev != nullptr && A->tree->dev_id == dev, HMAT_ERR_ARG,
              "the current device is not the one the H-matrices live on");
   error_estimate(C, A, B, X0, p, iters, reinterpret_cast<hipStream_t>(stream), err, norm_ab);
+  API_END
+}
+
+hmat_status hmat_gaussian_panel(int64_t n, int32_t ncol, uint64_t seed, double* out, void* stream) {
+  API_BEGIN
+  HM_REQUIRE(out != nullptr, HMAT_ERR_ARG, "out is NULL");
+  HM_REQUIRE(n >= 0 && ncol >= 0 && n < (int64_t(1) << 38), HMAT_ERR_ARG, "n must be in [0, 2^38) and ncol >= 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  launch_fill_gaussian(out, n, ncol, seed, s);
+  HM_CHECK_HIP(hipStreamSynchronize(s));
   API_END
 }
 

@@ -122,7 +122,7 @@ struct Pass {
     if (items.empty()) return;
     DevBuf<KApplyItem> d(items.size());
     d.upload(items, s);
-    const size_t maxg = 1u << 30;
+    const size_t maxg = size_t(max_groups(64));
     for (size_t b = 0; b < items.size(); b += maxg) {
       unsigned cnt = unsigned(std::min(maxg, items.size() - b));
       hipLaunchKernelGGL(k_kernel_apply, dim3(cnt), dim3(64), 0, s, d.p + b, xyz, kd);

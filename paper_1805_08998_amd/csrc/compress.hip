@@ -10,9 +10,9 @@ namespace hm {
 constexpr int NT = 256;
 
 // ---------------------------------------------------------------- Gaussian matrix
-__global__ void k_fill_gaussian(double* __restrict__ om, int64_t n, int32_t ncol, uint32_t k0,
+__global__ void k_fill_gaussian(double* __restrict__ om, int64_t n, int64_t i0, int32_t ncol, uint32_t k0,
                                 uint32_t k1) {
-  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int64_t i = i0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   int32_t j = blockIdx.y;
   if (i >= n || j >= ncol) return;
   U4 c{uint32_t(i), uint32_t(j), uint32_t(i >> 32), 0x0A11CE5u};
@@ -21,10 +21,15 @@ __global__ void k_fill_gaussian(double* __restrict__ om, int64_t n, int32_t ncol
 
 void launch_fill_gaussian(double* omega, int64_t n, int32_t ncol, uint64_t seed, hipStream_t s) {
   if (n <= 0 || ncol <= 0) return;
-  dim3 grid(unsigned((n + 255) / 256), unsigned(ncol));
-  hipLaunchKernelGGL(k_fill_gaussian, grid, dim3(256), 0, s, omega, n, ncol, uint32_t(seed),
-                     uint32_t(seed >> 32));
-  HM_CHECK_HIP(hipGetLastError());
+  // rows in launches of fewer than 2^32 work-items per grid row
+  const int64_t rows = 256 * max_groups(256);
+  for (int64_t i0 = 0; i0 < n; i0 += rows) {
+    const int64_t cnt = std::min(rows, n - i0);
+    dim3 grid(unsigned((cnt + 255) / 256), unsigned(ncol));
+    hipLaunchKernelGGL(k_fill_gaussian, grid, dim3(256), 0, s, omega, n, i0, ncol, uint32_t(seed),
+                       uint32_t(seed >> 32));
+    HM_CHECK_HIP(hipGetLastError());
+  }
 }
 
 // ---------------------------------------------------------------- helpers

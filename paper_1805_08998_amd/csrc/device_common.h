@@ -7,6 +7,10 @@
 
 namespace hm {
 
+// A dispatch holds fewer than 2^32 work-items (the grid size of an AQL dispatch packet is a
+// 32-bit count of work-items): the most workgroups of `threads` work-items one launch takes.
+constexpr int64_t max_groups(int threads) { return ((int64_t(1) << 32) - 1) / threads; }
+
 constexpr int WAVE = 64;
 
 __device__ __forceinline__ double wave_sum(double v) {

@@ -634,7 +634,7 @@ __global__ void __launch_bounds__(64) k_gather_mfma(const RowItem* __restrict__ 
 
 void launch_term_reduce(const TermItem* items, size_t n, const TDesc* td, const TInfo* ti, const TreeView& tv,
                         double* vbuf, hipStream_t s, bool lowp) {
-  const size_t maxg = size_t(1) << 30;
+  const size_t maxg = size_t(max_groups(64));
   for (size_t b = 0; b < n; b += maxg) {
     unsigned cnt = unsigned(std::min(maxg, n - b));
     if (lowp) hipLaunchKernelGGL(k_term_reduce<float>, dim3(cnt), dim3(64), 0, s, items + b, td, ti, tv, vbuf);
@@ -645,7 +645,7 @@ void launch_term_reduce(const TermItem* items, size_t n, const TDesc* td, const 
 
 void launch_gather_mfma(const RowItem* items, size_t n, const TDesc* td, const TInfo* ti, const HPair* hp,
                         const TreeView& tv, const double* vbuf, hipStream_t s, bool lowp) {
-  const size_t maxg = size_t(1) << 30;
+  const size_t maxg = size_t(max_groups(64));
   for (size_t b = 0; b < n; b += maxg) {
     unsigned cnt = unsigned(std::min(maxg, n - b));
     if (lowp) hipLaunchKernelGGL(k_gather_mfma<float>, dim3(cnt), dim3(64), 0, s, items + b, td, ti, hp, tv, vbuf);
@@ -675,7 +675,7 @@ void launch_fill_owner(const int64_t* pre, int ntask, int32_t* owner, hipStream_
 
 void launch_leaf_reduce(const int32_t* owner, int64_t nitems, const Task* tasks, const TDesc* td, const TreeView& tv,
                         const MatView& ma, const MatView& mb, double* ws, hipStream_t s, bool lowp) {
-  const int64_t maxg = int64_t(1) << 30;
+  const int64_t maxg = max_groups(64);
   for (int64_t b = 0; b < nitems; b += maxg) {
     unsigned cnt = unsigned(std::min(maxg, nitems - b));
     if (lowp)
@@ -689,7 +689,7 @@ void launch_leaf_reduce(const int32_t* owner, int64_t nitems, const Task* tasks,
 void launch_subtree_expand(const int32_t* owner, int64_t nitems, const Task* tasks, const TDesc* td,
                            const TreeView& tv, const MatView& ma, const MatView& mb, const double* ws,
                            hipStream_t s, bool lowp) {
-  const int64_t maxg = int64_t(1) << 30;
+  const int64_t maxg = max_groups(64);
   for (int64_t b = 0; b < nitems; b += maxg) {
     unsigned cnt = unsigned(std::min(maxg, nitems - b));
     if (lowp)
@@ -868,7 +868,7 @@ __global__ void __launch_bounds__(256) k_fused_terms4(const int32_t* __restrict_
 
 void launch_fused_terms4(const int32_t* tlist, size_t n, const TDesc* td, const TInfo* ti, const HPair* hp,
                          const TreeView& tv, hipStream_t s, bool lowp) {
-  const size_t maxg = size_t(1) << 30;
+  const size_t maxg = size_t(max_groups(256));
   for (size_t b = 0; b < n; b += maxg) {
     unsigned cnt = unsigned(std::min(maxg, n - b));
     if (lowp) hipLaunchKernelGGL(k_fused_terms4<float>, dim3(cnt), dim3(256), 0, s, tlist + b, td, ti, hp, tv);
@@ -879,7 +879,7 @@ void launch_fused_terms4(const int32_t* tlist, size_t n, const TDesc* td, const 
 
 void launch_fused_terms(const int32_t* tlist, size_t n, const TDesc* td, const TInfo* ti, const HPair* hp,
                         const TreeView& tv, hipStream_t s, bool lowp) {
-  const size_t maxg = size_t(1) << 30;
+  const size_t maxg = size_t(max_groups(64));
   for (size_t b = 0; b < n; b += maxg) {
     unsigned cnt = unsigned(std::min(maxg, n - b));
     if (lowp) hipLaunchKernelGGL(k_fused_terms<float>, dim3(cnt), dim3(64), 0, s, tlist + b, td, ti, hp, tv);
@@ -1043,7 +1043,7 @@ __global__ void __launch_bounds__(256) k_near_direct(const int32_t* __restrict__
 void launch_near_direct(const int32_t* items, int64_t nitems, const int32_t* blocks, const int64_t* coff,
                         const int32_t* pptr, const int32_t* pairs, const TreeView& tv, const MatView& ma,
                         const MatView& mb, double* cpool, hipStream_t s) {
-  const int64_t maxg = int64_t(1) << 30;
+  const int64_t maxg = max_groups(256);
   for (int64_t b = 0; b < nitems; b += maxg) {
     const unsigned cnt = unsigned(std::min(maxg, nitems - b));
     hipLaunchKernelGGL(k_near_direct, dim3(cnt), dim3(256), 0, s, items + 2 * b, blocks, coff, pptr, pairs, tv, ma,
@@ -1058,7 +1058,7 @@ __global__ void k_to_float(const double* __restrict__ src, float* __restrict__ d
 }
 
 void launch_to_float(const double* src, float* dst, int64_t n, hipStream_t s) {
-  const int64_t per = int64_t(256) * (int64_t(1) << 30);
+  const int64_t per = int64_t(256) * max_groups(256);
   for (int64_t b = 0; b < n; b += per) {
     const int64_t cnt = std::min(per, n - b);
     hipLaunchKernelGGL(k_to_float, dim3(unsigned((cnt + 255) / 256)), dim3(256), 0, s, src + b, dst + b, cnt);

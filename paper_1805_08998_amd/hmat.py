@@ -115,6 +115,7 @@ _SIGS = {
     "hmat_matvec": (C.c_int32, [_P, C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64, _P, C.c_int64, _P]),
     "hmat_error_estimate": (C.c_int32, [_P, _P, _P, _P, C.c_int32, C.c_int32, _P, _D, _D]),
     "hmat_matvec_noalloc": (C.c_int32, [_P, C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64, _P, C.c_int64, _P]),
+    "hmat_gaussian_panel": (C.c_int32, [C.c_int64, C.c_int32, C.c_uint64, _P, _P]),
     "hmat_block_count": (C.c_int32, [_P, _I64]),
     "hmat_block_get": (C.c_int32, [_P, C.c_int64, C.POINTER(hmat_block_desc), _D, _D]),
     "hmat_export": (C.c_int32, [_P, _I32, _I64, _D, _I64]),
@@ -309,6 +310,12 @@ def hmat_error_estimate(Cm, Am, Bm, x0_ptr, p, iters, stream=None):
     _check(lib().hmat_error_estimate(Cm, Am, Bm, C.c_void_p(x0_ptr), p, iters, C.c_void_p(stream or 0),
                                      C.byref(err), C.byref(nrm)))
     return err.value, nrm.value
+
+
+def hmat_gaussian_panel(n, ncol, seed, out_ptr, stream=None):
+    """Omega(i, j), i < n, j < ncol, of the randomized scheme into the device memory at out_ptr
+    (n x ncol, column-major)."""
+    _check(lib().hmat_gaussian_panel(n, ncol, seed, C.c_void_p(out_ptr), C.c_void_p(stream or 0)))
 
 
 def hmat_to_dense(m, n, order=1):
