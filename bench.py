@@ -216,16 +216,32 @@ def train_predictor(H, configs, names, epochs, cache=None, eps=None, target="wid
 
 def copy_probe():
     """A plain device copy of known size (1 GiB read, 1 GiB written per launch,
-    five launches), the calibration run for the HBM traffic counters."""
+    five launches), the calibration run for the HBM traffic counters. Also reports the
+    rates the device reaches on plain streaming work (the copy, and a sum that only
+    reads), timed with events on the stream the copies run on: the practical ceiling
+    against which the apply kernels' measured HBM traffic rates are read."""
     import torch
     nbytes = 1 << 30
     x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
     torch.cuda.synchronize()
-    for _ in range(5):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    y.copy_(x)  # the first launch of each is not timed
+    ev[0].record()
+    for _ in range(4):
         y.copy_(x)
+    ev[1].record()
+    s = x.sum()
+    ev[2].record()
+    for _ in range(4):
+        s = x.sum()
+    ev[3].record()
     torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "launches": 5}))
+    copy_s = ev[0].elapsed_time(ev[1]) / 1e3 / 4
+    read_s = ev[2].elapsed_time(ev[3]) / 1e3 / 4
+    print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "launches": 5,
+                      "copy_GB_s": 2 * nbytes / copy_s / 1e9, "read_GB_s": nbytes / read_s / 1e9,
+                      "sum_check": float(s) == nbytes // 8}))
 
 
 def product_source_hash():
