@@ -200,6 +200,10 @@ typedef struct {
    * orthogonalisation and projections after the first residual check): the most that a
    * better first sketch width (HMAT_RANK_PREDICT) can save */
   double t_growth;
+  /* passes over chunks of targets (sketch, projection and identity-panel passes), and those
+   * of them that launched only the work items of their active targets (full_passes) */
+  int64_t n_passes;
+  int64_t n_sparse_passes;
 } hmat_stats;
 
 /* Kernel families of hmat_stats.kern_* */
@@ -247,7 +251,12 @@ typedef struct {
                              (S_H empty) are truncated exactly by the SVD of their low-rank sum
                              (Algorithm 5) when it fits the 64-column panels; 0 (default): every
                              target uses `scheme` */
-  int32_t pad2;
+  int32_t full_passes; /* 0 (default): a pass over a chunk of targets in which at most an
+                          eighth of them are active (a growth round, the later 16-column
+                          identity panels of a chunk's widest targets) launches only the work
+                          items of the active ones; each launched item computes what it computes
+                          in a full pass, so results are bit-identical. 1: every pass launches
+                          all work items of its chunk (inactive ones exit at once) */
 } hmat_opts;
 
 /* Low-rank schemes of Section 4 (hmat_opts.scheme). Every scheme touches a target's

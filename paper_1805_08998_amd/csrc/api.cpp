@@ -214,6 +214,7 @@ Opts resolve_opts(const hmat_opts* o) {
   HM_REQUIRE(r.o.k_fixed >= 0 && r.o.k_fixed <= 64, HMAT_ERR_ARG, "k_fixed must be in [0, 64]");
   HM_REQUIRE(r.o.subspace_iters >= 0 && r.o.subspace_iters <= 8, HMAT_ERR_ARG, "subspace_iters must be in [0, 8]");
   HM_REQUIRE(r.o.exact_lowrank == 0 || r.o.exact_lowrank == 1, HMAT_ERR_ARG, "exact_lowrank must be 0 or 1");
+  HM_REQUIRE(r.o.full_passes == 0 || r.o.full_passes == 1, HMAT_ERR_ARG, "full_passes must be 0 or 1");
   const bool plain_randomized = r.o.scheme == HMAT_SCHEME_RANDOMIZED && r.o.k_fixed == 0;
   HM_REQUIRE(r.o.rank_mode != HMAT_RANK_PREDICT || plain_randomized, HMAT_ERR_ARG,
              "HMAT_RANK_PREDICT sizes the first sketch of the adaptive randomized scheme only");

@@ -578,19 +578,25 @@ int64_t subtree_ws(const Ctx& c, int mat, int32_t q) {
   return (dm.hkpref[c.dfs.hi[q]] - dm.hkpref[c.dfs.lo[q]]) * PW;
 }
 
-// Leaf reductions (and expansions) of a task list; X and widths of target tasks come from td.
+// Leaf reductions (and expansions) of nl (nr) work items of a task array, owner tables
+// lown and rown; X and widths of target tasks come from td.
+void run_task_items(Ctx& c, const Task* tasks, int64_t nl, const int32_t* lown, int64_t nr, const int32_t* rown,
+                    const TDesc* td, double* ws, bool expand, bool lowp) {
+  if (nl > 0) {
+    c.timer.begin(K_LEAF);
+    launch_leaf_reduce(lown, nl, tasks, td, c.tv, c.ma, c.mb, ws, c.s, lowp);
+    c.timer.end();
+  }
+  if (expand && nr > 0) {
+    c.timer.begin(K_EXPAND);
+    launch_subtree_expand(rown, nr, tasks, td, c.tv, c.ma, c.mb, ws, c.s, lowp);
+    c.timer.end();
+  }
+}
+
 void run_tasks(Ctx& c, TaskList& L, const TDesc* td, double* ws, bool expand, bool lowp = false) {
   if (L.tasks.empty()) return;
-  if (L.lpre.back() > 0) {
-    c.timer.begin(K_LEAF);
-    launch_leaf_reduce(L.d_lown.p, L.lpre.back(), L.d_tasks.p, td, c.tv, c.ma, c.mb, ws, c.s, lowp);
-    c.timer.end();
-  }
-  if (expand && L.rpre.back() > 0) {
-    c.timer.begin(K_EXPAND);
-    launch_subtree_expand(L.d_rown.p, L.rpre.back(), L.d_tasks.p, td, c.tv, c.ma, c.mb, ws, c.s, lowp);
-    c.timer.end();
-  }
+  run_task_items(c, L.d_tasks.p, L.lpre.back(), L.d_lown.p, L.rpre.back(), L.d_rown.p, td, ws, expand, lowp);
 }
 
 // Term creation is split so that the host part of a subtree batch can be prepared on a
@@ -887,6 +893,18 @@ struct Chunk {
   std::vector<Coef> g_leaf, g_exp;    // work of group g's task (per column)
   std::vector<Coef> s1_leaf, s1_exp;  // per target: its stage-1 work as if run alone
   std::vector<TDesc> tdx;             // pass descriptors of the targets, then of the groups
+  // Sparse passes. In a pass where few of the chunk's targets are active (a growth round,
+  // the later 16-column identity panels of a chunk's widest targets), launching every work
+  // item of the chunk costs far more than the active ones' work: each inactive item still
+  // reads its task and descriptor before it exits. Such a pass launches only the work items
+  // of its active descriptors. `sp_ptr` / `sp_idx`: per list (t1f, t2f, t1t, t2t, term
+  // items, gf, gt, small, small4), the entries of each descriptor (targets, then stage-1
+  // groups; entries with no descriptor last), built with the chunk.
+  bool sp_built = false;
+  std::vector<int32_t> sp_ptr[9], sp_idx[9];
+  std::vector<char> sp_host;
+  DevBuf<char> sp_dev;
+  DevBuf<int32_t> sp_own[4];  // owner tables of the compact lists: leaf and expand, two lists
   // recorded on the product's stream after the chunk's last kernel when the chunk is
   // recycled: the builder's stream waits on it before reusing or freeing the device buffers
   hipEvent_t done = nullptr;
@@ -935,6 +953,7 @@ struct Chunk {
     g_exp.clear();
     s1_leaf.clear();
     s1_exp.clear();
+    sp_built = false;
   }
 };
 
@@ -984,6 +1003,8 @@ int64_t target_cost(const Ctx& c, int32_t b, bool far, const Opts& o, int cap) {
   int64_t panels = far ? (m * (cap + o.o.probes) + n * cap + 2 * cap * cap + cap) : 0;
   return 8 * (v + pr + panels) + 512;
 }
+
+void build_sparse_index(Chunk& ch);
 
 void build_chunk(const Ctx& c, Chunk& ch, bool features) {
   const Tree& t = *c.t;
@@ -1139,6 +1160,9 @@ void build_chunk(const Ctx& c, Chunk& ch, bool features) {
     std::vector<int32_t> fill(ch.g_ptr.begin(), ch.g_ptr.end() - 1);
     for (const auto& gm : members) ch.g_mem[fill[gm.first]++] = gm.second;
   }
+  // built here, on the builder's thread while the device runs the previous chunk, rather
+  // than at the chunk's first sparse pass, when the device would wait for it
+  build_sparse_index(ch);
 }
 
 void upload_chunk(Chunk& ch, hipStream_t s) {
@@ -1167,6 +1191,140 @@ void upload_chunk(Chunk& ch, hipStream_t s) {
 }
 
 // One application of every target's operator in the chunk (forward: S X, transposed: S^T X).
+// Index of the chunk's work items by pass descriptor (see Chunk::sp_ptr).
+void build_sparse_index(Chunk& ch) {
+  const int32_t nd = int32_t(ch.blocks.size() + ch.g_leaf.size());  // targets, then stage-1 groups
+  auto csr = [&](int li, size_t n, auto key) {
+    std::vector<int32_t>& ptr = ch.sp_ptr[li];
+    std::vector<int32_t>& idx = ch.sp_idx[li];
+    ptr.assign(size_t(nd) + 2, 0);
+    for (size_t i = 0; i < n; ++i) {
+      const int32_t k = key(i);
+      ptr[size_t(k >= 0 && k < nd ? k : nd) + 1]++;
+    }
+    for (size_t j = 0; j + 1 < ptr.size(); ++j) ptr[j + 1] += ptr[j];
+    idx.resize(n);
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+    for (size_t i = 0; i < n; ++i) {
+      const int32_t k = key(i);
+      idx[size_t(fill[size_t(k >= 0 && k < nd ? k : nd)]++)] = int32_t(i);
+    }
+  };
+  TaskList* lists[4] = {&ch.t1f, &ch.t2f, &ch.t1t, &ch.t2t};
+  for (int li = 0; li < 4; ++li) {
+    const TaskList& L = *lists[li];
+    csr(li, L.tasks.size(), [&](size_t i) { return L.tasks[i].t; });
+  }
+  csr(4, ch.term_items.size(), [&](size_t i) { return ch.term_items[i].t; });
+  csr(5, ch.gf.size(), [&](size_t i) { return ch.gf[i].owner; });
+  csr(6, ch.gt.size(), [&](size_t i) { return ch.gt[i].owner; });
+  csr(7, ch.small.size(), [&](size_t i) { return ch.small[i]; });
+  csr(8, ch.small4.size(), [&](size_t i) { return ch.small4[i]; });
+  ch.sp_built = true;
+}
+
+// One pass over the work items of the active descriptors only (ch.tdx holds the pass's
+// descriptors, already on the device as dtd). Every launched item does what it does in a
+// full pass, so the results are the same bit for bit.
+void run_pass_sparse(Ctx& c, Chunk& ch, const TDesc* dtd, bool trans, bool lowp) {
+  hipStream_t s = c.s;
+  if (!ch.sp_built) build_sparse_index(ch);
+  const int32_t nd = int32_t(ch.tdx.size());
+  HM_REQUIRE(size_t(nd) + 2 == ch.sp_ptr[0].size(), HMAT_ERR_INTERNAL, "sparse pass index out of date");
+  std::vector<int32_t> act;
+  for (int32_t j = 0; j < nd; ++j)
+    if (ch.tdx[j].w > 0) act.push_back(j);
+  act.push_back(nd);  // entries with no descriptor
+  std::vector<char>& h = ch.sp_host;
+  h.clear();
+  auto section = [&](size_t bytes) {
+    const size_t off = (h.size() + 255) & ~size_t(255);
+    h.resize(off + bytes);
+    return off;
+  };
+  // gathers the active entries of list li from src into a new section; returns (offset, count)
+  auto gather = [&](int li, const auto& src) {
+    using T = typename std::decay_t<decltype(src)>::value_type;
+    size_t cnt = 0;
+    for (int32_t j : act) cnt += size_t(ch.sp_ptr[li][size_t(j) + 1] - ch.sp_ptr[li][size_t(j)]);
+    const size_t off = section(cnt * sizeof(T));
+    T* out = reinterpret_cast<T*>(h.data() + off);
+    size_t k = 0;
+    for (int32_t j : act)
+      for (int32_t e = ch.sp_ptr[li][size_t(j)]; e < ch.sp_ptr[li][size_t(j) + 1]; ++e) out[k++] = src[size_t(ch.sp_idx[li][size_t(e)])];
+    return std::make_pair(off, cnt);
+  };
+  // task lists of this direction: tasks, and the prefix sums of their leaf and expansion items
+  struct Compact {
+    size_t tasks = 0, lpre = 0, rpre = 0, n = 0;
+    int64_t nl = 0, nr = 0;
+  } cl[2];
+  TaskList* lists[2] = {trans ? &ch.t1t : &ch.t1f, trans ? &ch.t2t : &ch.t2f};
+  for (int x = 0; x < 2; ++x) {
+    const int li = (trans ? 2 : 0) + x;
+    const TaskList& L = *lists[x];
+    auto tk = gather(li, L.tasks);
+    cl[x].tasks = tk.first;
+    cl[x].n = tk.second;
+    cl[x].lpre = section((tk.second + 1) * sizeof(int64_t));
+    cl[x].rpre = section((tk.second + 1) * sizeof(int64_t));
+    int64_t* lp = reinterpret_cast<int64_t*>(h.data() + cl[x].lpre);
+    int64_t* rp = reinterpret_cast<int64_t*>(h.data() + cl[x].rpre);
+    lp[0] = rp[0] = 0;
+    size_t k = 0;
+    for (int32_t j : act)
+      for (int32_t e = ch.sp_ptr[li][size_t(j)]; e < ch.sp_ptr[li][size_t(j) + 1]; ++e, ++k) {
+        const size_t i = size_t(ch.sp_idx[li][size_t(e)]);
+        lp[k + 1] = lp[k] + (L.lpre[i + 1] - L.lpre[i]);
+        rp[k + 1] = rp[k] + (L.rpre[i + 1] - L.rpre[i]);
+      }
+    cl[x].nl = lp[k];
+    cl[x].nr = rp[k];
+  }
+  const auto terms = gather(4, ch.term_items);
+  const auto rows = trans ? gather(6, ch.gt) : gather(5, ch.gf);
+  const auto small = gather(7, ch.small);
+  const auto small4 = gather(8, ch.small4);
+  ch.sp_dev.upload(h, s);  // one synchronous copy
+  const char* d = ch.sp_dev.p;
+  double* ws = trans ? ch.wst.p : ch.wsf.p;
+  for (int x = 0; x < 2; ++x) {
+    if (cl[x].n == 0) continue;
+    DevBuf<int32_t>& lown = ch.sp_own[2 * x];
+    DevBuf<int32_t>& rown = ch.sp_own[2 * x + 1];
+    if (lown.n < size_t(2 * std::max<int64_t>(cl[x].nl, 1))) lown.alloc(size_t(2 * std::max<int64_t>(cl[x].nl, 1)));
+    if (rown.n < size_t(2 * std::max<int64_t>(cl[x].nr, 1))) rown.alloc(size_t(2 * std::max<int64_t>(cl[x].nr, 1)));
+    launch_fill_owner(reinterpret_cast<const int64_t*>(d + cl[x].lpre), int(cl[x].n), lown.p, s);
+    launch_fill_owner(reinterpret_cast<const int64_t*>(d + cl[x].rpre), int(cl[x].n), rown.p, s);
+    run_task_items(c, reinterpret_cast<const Task*>(d + cl[x].tasks), cl[x].nl, lown.p, cl[x].nr, rown.p, dtd, ws,
+                   true, lowp);
+  }
+  if (terms.second) {
+    c.timer.begin(K_TERM);
+    launch_term_reduce(reinterpret_cast<const TermItem*>(d + terms.first), terms.second, dtd, ch.d_info.p, c.tv,
+                       ch.vbuf.p, s, lowp);
+    c.timer.end();
+  }
+  if (rows.second) {
+    c.timer.begin(K_GATHER);
+    launch_gather_mfma(reinterpret_cast<const RowItem*>(d + rows.first), rows.second, dtd, ch.d_info.p, ch.d_pairs.p,
+                       c.tv, ch.vbuf.p, s, lowp);
+    c.timer.end();
+  }
+  if (small.second) {
+    c.timer.begin(K_FUSED);
+    launch_fused_terms(reinterpret_cast<const int32_t*>(d + small.first), small.second, dtd, ch.d_info.p,
+                       ch.d_pairs.p, c.tv, s, lowp);
+    c.timer.end();
+  }
+  if (small4.second) {
+    c.timer.begin(K_FUSED4);
+    launch_fused_terms4(reinterpret_cast<const int32_t*>(d + small4.first), small4.second, dtd, ch.d_info.p,
+                        ch.d_pairs.p, c.tv, s, lowp);
+    c.timer.end();
+  }
+}
+
 void run_pass(Ctx& c, Chunk& ch, const std::vector<TDesc>& td, bool trans, bool lowp = false) {
   hipStream_t s = c.s;
   // descriptors of the targets, then of the stage-1 groups (forward passes): a group takes
@@ -1204,6 +1362,14 @@ void run_pass(Ctx& c, Chunk& ch, const std::vector<TDesc>& td, bool trans, bool 
         account(c.st, K_GATHER, ch.coef[K_GATHER][d][i], td[i].w);
       }
     }
+  size_t nact = 0;
+  for (size_t i = 0; i < nt; ++i) nact += td[i].w > 0;
+  c.st.n_passes++;
+  if (!c.opts.o.full_passes && nact * 8 <= nt && nt >= 64) {
+    c.st.n_sparse_passes++;
+    run_pass_sparse(c, ch, dtd, trans, lowp);
+    return;
+  }
   if (!trans) {
     run_tasks(c, ch.t1f, dtd, ch.wsf.p, true, lowp);
     run_tasks(c, ch.t2f, dtd, ch.wsf.p, true, lowp);
@@ -2505,6 +2671,12 @@ void add_stats(hmat_stats& a, const hmat_stats& b) {
   a.n_terms += b.n_terms;
   a.n_leaf_pairs += b.n_leaf_pairs;
   a.t_near_panels += b.t_near_panels;
+  a.scheme_steps += b.scheme_steps;
+  a.n_exact_lowrank += b.n_exact_lowrank;
+  a.n_svd_sweep_cap += b.n_svd_sweep_cap;
+  a.t_growth += b.t_growth;
+  a.n_passes += b.n_passes;
+  a.n_sparse_passes += b.n_sparse_passes;
 }
 }  // namespace
 

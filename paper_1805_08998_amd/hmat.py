@@ -54,7 +54,7 @@ class hmat_stats(C.Structure):
                 ("streams_used", C.c_int32), ("pad_s", C.c_int32), ("n_near_direct", C.c_int64),
                 ("t_near_panels", C.c_double), ("n_terms", C.c_int64), ("n_leaf_pairs", C.c_int64),
                 ("scheme_steps", C.c_int64), ("n_exact_lowrank", C.c_int64), ("n_svd_sweep_cap", C.c_int64),
-                ("t_growth", C.c_double)]
+                ("t_growth", C.c_double), ("n_passes", C.c_int64), ("n_sparse_passes", C.c_int64)]
 
     def as_dict(self):
         d = {}
@@ -71,7 +71,7 @@ class hmat_opts(C.Structure):
                 ("rank_model", C.c_void_p), ("stats", C.POINTER(hmat_stats)),
                 ("workspace_limit", C.c_int64), ("streams", C.c_int32), ("scheme", C.c_int32),
                 ("k_fixed", C.c_int32), ("subspace_iters", C.c_int32), ("exact_lowrank", C.c_int32),
-                ("pad2", C.c_int32)]
+                ("full_passes", C.c_int32)]
 
 
 class hmat_kernel(C.Structure):

@@ -151,3 +151,34 @@ def test_product_with_identity_and_zero(H):
         H.hmat_destroy(I)
     H.hmat_destroy(A)
     H.hmat_tree_destroy(t)
+
+
+@pytest.mark.parametrize("eps,precision", [(1e-6, 0), (1e-9, 0), (1e-6, 1)])
+def test_sparse_passes_bit_identical(H, eps, precision):
+    """A pass in which at most an eighth of a chunk's targets are active (growth rounds,
+    the later identity panels of a chunk's widest targets) launches only their work items.
+    The product equals, bit for bit, the one whose passes launch every work item."""
+    import ctypes
+    pts = jitter(fibonacci_sphere(8192), 1e-3, seed=11)
+    t = H.hmat_build_tree(pts, 32, 0.8, 0)
+    A, _ = H.hmat_assemble(t, "laplace_4pi", 1.0, 0.0, eps_in=1e-10)
+    B, _ = H.hmat_assemble(t, "exp", 1.0, 1.0, eps_in=1e-10)
+    out = []
+    for full in (0, 1):
+        st = H.hmat_stats()
+        o = H.hmat_opts_default(full_passes=full, precision=precision)
+        o.stats = ctypes.pointer(st)
+        C, code = H.hmat_multiply(A, B, eps, o)
+        assert code == 0
+        out.append((H.hmat_export(C), st.n_passes, st.n_sparse_passes, st.n_growth_rounds, st.t_total))
+        H.hmat_destroy(C)
+    for h in (A, B):
+        H.hmat_destroy(h)
+    H.hmat_tree_destroy(t)
+    (r0, o0, p0), n0, s0, g0, t0 = out[0]
+    (r1, o1, p1), n1, s1, g1, t1 = out[1]
+    print(f"eps {eps} precision {precision}: passes {n0} ({s0} sparse) vs {n1} ({s1}), growth rounds {g0}, "
+          f"product {t0:.3f} s vs {t1:.3f} s", flush=True)
+    assert s0 > 0 and s1 == 0 and n0 == n1
+    assert np.array_equal(r0, r1) and np.array_equal(o0, o1)
+    assert p0.tobytes() == p1.tobytes()
