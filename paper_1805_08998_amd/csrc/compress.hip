@@ -62,13 +62,97 @@ __device__ double norm2_col(const double* v, int m, double* red) {
   return block_sum<NT>(acc, red);
 }
 
+// Targets of at most SMALL_M rows take the one-wave kernels below (four targets per
+// workgroup, lane l owning rows l and l + 64): their Gram-Schmidt steps are wave sums with
+// no barriers, where a workgroup of NT threads would leave most of its threads idle and
+// wait at a barrier several times per column. Larger targets take the NT-thread kernels.
+constexpr int SMALL_M = 128;
+constexpr int HMAX = 128;  // Gram-Schmidt coefficients per column: r < cap + probes
+
+// v -= Q[:, :r] (Q[:, :r]^T v) for a vector v held as (v0, v1) = rows (lane, lane + 64):
+// all r coefficients from the same v (classical Gram-Schmidt), kept in the wave's LDS row.
+__device__ __forceinline__ void project_out_wave(const double* __restrict__ Q, int m, int r, double& v0, double& v1,
+                                                 int lane, bool in0, bool in1, double* hs) {
+  for (int j = 0; j < r; ++j) {
+    const double* q = Q + int64_t(j) * m;
+    const double q0 = in0 ? q[lane] : 0.0, q1 = in1 ? q[lane + 64] : 0.0;
+    const double hj = wave_sum(q0 * v0 + q1 * v1);
+    if (lane == 0) hs[j] = hj;
+  }
+  // one wave: its LDS accesses complete in issue order; keep the compiler from moving them
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_wave_barrier();
+  for (int j = 0; j < r; ++j) {
+    const double* q = Q + int64_t(j) * m;
+    const double hj = hs[j];
+    if (in0) v0 -= q[lane] * hj;
+    if (in1) v1 -= q[lane + 64] * hj;
+  }
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_wave_barrier();
+}
+
+__global__ void __launch_bounds__(NT) k_orth_append_w(CTarget* __restrict__ tg, int nt, int src, int cnt, int cap) {
+  __shared__ double hsh[NT / 64][HMAX];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t = blockIdx.x * (NT / 64) + wv;
+  if (t >= nt) return;
+  CTarget& T = tg[t];
+  if (!T.active || T.m > SMALL_M) return;
+  double* hs = hsh[wv];
+  const int m = T.m;
+  double* Y = T.Y;
+  int r = T.r;
+  const int cnt_t = (src == 0 && T.w0 > 0 && T.w0 < cnt) ? T.w0 : cnt;
+  const bool in0 = lane < m, in1 = lane + 64 < m;
+  for (int c = src; c < src + cnt_t; ++c) {
+    const double* v = Y + int64_t(c) * m;
+    double v0 = in0 ? v[lane] : 0.0, v1 = in1 ? v[lane + 64] : 0.0;
+    const double n0 = wave_uniform(wave_sum(v0 * v0 + v1 * v1));
+    for (int pass = 0; pass < 2; ++pass) project_out_wave(Y, m, r, v0, v1, lane, in0, in1, hs);
+    const double n1 = wave_uniform(wave_sum(v0 * v0 + v1 * v1));
+    const bool keep = (r < cap) && n1 > 0.0 && n1 > 1e-26 * n0;  // relative residual > 1e-13
+    if (keep) {
+      const double inv = 1.0 / sqrt(n1);
+      double* dst = Y + int64_t(r) * m;
+      if (in0) dst[lane] = v0 * inv;
+      if (in1) dst[lane + 64] = v1 * inv;
+      ++r;
+    }
+  }
+  if (lane == 0) T.r = r;
+}
+
+__global__ void __launch_bounds__(NT) k_probe_residual_w(CTarget* __restrict__ tg, int nt, int cap, int g) {
+  __shared__ double hsh[NT / 64][HMAX];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t = blockIdx.x * (NT / 64) + wv;
+  if (t >= nt) return;
+  CTarget& T = tg[t];
+  if (!T.active || T.m > SMALL_M) return;
+  double* hs = hsh[wv];
+  const int m = T.m, r = T.r;
+  double* Y = T.Y;
+  const bool in0 = lane < m, in1 = lane + 64 < m;
+  double e2 = 0.0;
+  for (int c = cap; c < cap + g; ++c) {
+    double* v = Y + int64_t(c) * m;
+    double v0 = in0 ? v[lane] : 0.0, v1 = in1 ? v[lane + 64] : 0.0;
+    for (int pass = 0; pass < 2; ++pass) project_out_wave(Y, m, r, v0, v1, lane, in0, in1, hs);
+    e2 += wave_uniform(wave_sum(v0 * v0 + v1 * v1));
+    if (in0) v[lane] = v0;
+    if (in1) v[lane + 64] = v1;
+  }
+  if (lane == 0) T.E2 = e2 / double(g);
+}
+
 // ---------------------------------------------------------------- orthogonalisation
 __global__ void __launch_bounds__(NT) k_orth_append(CTarget* __restrict__ tg, int nt, int src, int cnt,
                                                     int cap) {
   __shared__ double h[128];
   __shared__ double red[NT / 64];
   CTarget& T = tg[blockIdx.x];
-  if (!T.active) return;
+  if (!T.active || T.m <= SMALL_M) return;
   const int m = T.m;
   double* Y = T.Y;
   int r = T.r;
@@ -96,6 +180,9 @@ __global__ void __launch_bounds__(NT) k_orth_append(CTarget* __restrict__ tg, in
 
 void launch_orth_append(CTarget* t, int nt, int src, int cnt, const CParams& p, hipStream_t s) {
   if (nt <= 0) return;
+  if (p.cap > HMAX) throw Error(HMAT_ERR_INTERNAL, "column capacity above the Gram-Schmidt buffer");
+  hipLaunchKernelGGL(k_orth_append_w, dim3((nt + NT / 64 - 1) / (NT / 64)), dim3(NT), 0, s, t, nt, src, cnt, p.cap);
+  HM_CHECK_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_orth_append, dim3(nt), dim3(NT), 0, s, t, nt, src, cnt, p.cap);
   HM_CHECK_HIP(hipGetLastError());
 }
@@ -105,7 +192,7 @@ __global__ void __launch_bounds__(NT) k_probe_residual(CTarget* __restrict__ tg,
   __shared__ double h[128];
   __shared__ double red[NT / 64];
   CTarget& T = tg[blockIdx.x];
-  if (!T.active) return;
+  if (!T.active || T.m <= SMALL_M) return;
   const int m = T.m, r = T.r;
   double* Y = T.Y;
   double e2 = 0.0;
@@ -122,6 +209,9 @@ __global__ void __launch_bounds__(NT) k_probe_residual(CTarget* __restrict__ tg,
 
 void launch_probe_residual(CTarget* t, int nt, const CParams& p, hipStream_t s) {
   if (nt <= 0) return;
+  if (p.cap > HMAX) throw Error(HMAT_ERR_INTERNAL, "column capacity above the Gram-Schmidt buffer");
+  hipLaunchKernelGGL(k_probe_residual_w, dim3((nt + NT / 64 - 1) / (NT / 64)), dim3(NT), 0, s, t, nt, p.cap, p.g);
+  HM_CHECK_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_probe_residual, dim3(nt), dim3(NT), 0, s, t, nt, p.cap, p.g);
   HM_CHECK_HIP(hipGetLastError());
 }

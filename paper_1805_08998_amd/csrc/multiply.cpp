@@ -610,6 +610,12 @@ struct CreatePrep {
   int64_t pos = 0;
   double kern_bytes[8] = {}, kern_flops[8] = {};
   double alg_bytes = 0, alg_flops = 0, t_lists = 0;
+  // the terms' device descriptors in the order of `which`, packed and uploaded by the
+  // preparing thread (stage_terms): publish_terms then only scatters them
+  std::vector<Term> packed;
+  DevBuf<int32_t> d_ids;
+  DevBuf<Term> d_src;
+  bool staged = false;
 };
 
 int64_t layout_terms(Ctx& c, const std::vector<int32_t>& which) {
@@ -628,6 +634,7 @@ void prepare_terms(Ctx& c, const std::vector<int32_t>& which, double* P, int64_t
   const Tree& t = *c.t;
   const double th0 = now_seconds();
   pr.pos = pos;
+  pr.staged = false;
   for (int k = 0; k < 8; ++k) pr.kern_bytes[k] = pr.kern_flops[k] = 0;
   pr.alg_bytes = pr.alg_flops = 0;
   TaskList& ff = pr.ff;
@@ -756,6 +763,17 @@ void prepare_terms(Ctx& c, const std::vector<int32_t>& which, double* P, int64_t
   pr.t_lists = now_seconds() - th0;
 }
 
+// Packs the descriptors of the terms in `which` (final once prepare_terms has run) and
+// uploads them on stream s, on the preparing thread, so that the device does not wait for
+// this between a batch's term creation and its targets.
+void stage_terms(const Ctx& c, const std::vector<int32_t>& which, CreatePrep& pr, hipStream_t s) {
+  pr.packed.resize(which.size());
+  for (size_t i = 0; i < which.size(); ++i) pr.packed[i] = c.hterms[size_t(which[i])];
+  pr.d_ids.upload(which, s);
+  pr.d_src.upload(pr.packed, s);
+  pr.staged = true;
+}
+
 void execute_terms(Ctx& c, CreatePrep& pr, double* P, DevBuf<float>& pool32_out) {
   hipStream_t s = c.s;
   for (int k = 0; k < 8; ++k) {
@@ -800,8 +818,9 @@ void create_terms(Ctx& c, const std::vector<int32_t>& which, DevBuf<double>& poo
   execute_terms(c, pr, pool_out.p, pool32_out);
 }
 
-// Device descriptors of the terms in `which` (only these changed since the last call).
-void publish_terms(Ctx& c, const std::vector<int32_t>& which) {
+// Device descriptors of the terms in `which` (only these changed since the last call);
+// `pr`, when given and staged, holds them packed and uploaded already.
+void publish_terms(Ctx& c, const std::vector<int32_t>& which, CreatePrep* pr = nullptr) {
   const double t0 = now_seconds();
   struct Acc {
     Ctx& c;
@@ -811,14 +830,27 @@ void publish_terms(Ctx& c, const std::vector<int32_t>& which) {
   if (c.terms.n < c.hterms.size()) c.terms.alloc(c.hterms.size());
   if (which.empty()) return;
   static thread_local std::vector<Term> packed_keep;
-  std::vector<Term>& packed = packed_keep;
-  packed.resize(which.size());
-  for (size_t i = 0; i < which.size(); ++i) packed[i] = c.hterms[which[i]];
-  DevBuf<int32_t> ids;
-  ids.upload(which, c.s);
-  DevBuf<Term> src;
-  src.upload(packed, c.s);
-  launch_scatter_terms(ids.p, src.p, c.terms.p, int64_t(which.size()), c.s);
+  DevBuf<int32_t> ids_here;
+  DevBuf<Term> src_here;
+  const int32_t* ids;
+  const Term* src;
+  const std::vector<Term>* packed_p;
+  if (pr && pr->staged && pr->packed.size() == which.size()) {
+    ids = pr->d_ids.p;
+    src = pr->d_src.p;
+    packed_p = &pr->packed;
+  } else {
+    std::vector<Term>& packed = packed_keep;
+    packed.resize(which.size());
+    for (size_t i = 0; i < which.size(); ++i) packed[i] = c.hterms[which[i]];
+    ids_here.upload(which, c.s);
+    src_here.upload(packed, c.s);
+    ids = ids_here.p;
+    src = src_here.p;
+    packed_p = &packed;
+  }
+  const std::vector<Term>& packed = *packed_p;
+  launch_scatter_terms(ids, src, c.terms.p, int64_t(which.size()), c.s);
   if (c.lowp) {
     // the same terms over the float copies (TermT<float> has the layout of TermT<double>)
     static_assert(sizeof(Term32) == sizeof(Term), "term layouts differ");
@@ -843,7 +875,7 @@ void publish_terms(Ctx& c, const std::vector<int32_t>& which) {
     }
     DevBuf<Term32> src32;
     src32.upload(p32, c.s);
-    launch_scatter_terms(ids.p, reinterpret_cast<const Term*>(src32.p), reinterpret_cast<Term*>(c.terms32.p),
+    launch_scatter_terms(ids, reinterpret_cast<const Term*>(src32.p), reinterpret_cast<Term*>(c.terms32.p),
                          int64_t(which.size()), c.s);
     c.tv.terms32 = c.terms32.p;
   }
@@ -885,6 +917,12 @@ struct Chunk {
   bool share_s1 = true;
   std::vector<uint8_t> direct;
   std::vector<int32_t> dpptr, dpairs;  // per direct target (chunk order): dense pairs (A block, B block)
+  // direct kernel work, prepared by the builder: (direct target, 64-row block << 16) items,
+  // the direct targets' chunk positions, and their algorithmic bytes and flops
+  std::vector<int32_t> ditems, dpos;
+  std::vector<double> dby, dfl;
+  DevBuf<int32_t> d_ditems, d_dblk, d_dpptr, d_dpairs;
+  DevBuf<int64_t> d_dco;
   // Forward stage 1 of a pair, B[rho, sigma] X, depends only on the pair block and on X, and
   // in a forward pass X is fixed by sigma (rows of Omega, or identity columns, at a column
   // offset common to the pass). One stage-1 task per pair block serves all targets that hold
@@ -947,6 +985,10 @@ struct Chunk {
     direct.clear();
     dpptr.clear();
     dpairs.clear();
+    ditems.clear();
+    dpos.clear();
+    dby.clear();
+    dfl.clear();
     g_ptr.clear();
     g_mem.clear();
     g_leaf.clear();
@@ -1005,6 +1047,40 @@ int64_t target_cost(const Ctx& c, int32_t b, bool far, const Opts& o, int cap) {
 }
 
 void build_sparse_index(Chunk& ch);
+
+// Work items of the direct nearfield kernel and each direct target's algorithmic bytes and
+// flops (terms of the target and of its ancestors, dense x dense pairs): on the builder's
+// thread, so that the device does not wait for them.
+void prepare_direct(const Ctx& c, Chunk& ch) {
+  const Tree& t = *c.t;
+  const int nt = int(ch.blocks.size());
+  for (int i = 0; i < nt; ++i) {
+    if (!ch.direct[i]) continue;
+    const int32_t b = ch.blocks[i];
+    const int m = c.m_of(b), n = c.n_of(b);
+    const int k = int32_t(ch.dpos.size());
+    for (int rb = 0; rb < (m + 63) / 64; ++rb) {
+      ch.ditems.push_back(k);
+      ch.ditems.push_back(rb << 16);
+    }
+    double by = 8.0 * m * n, fl = 0.0;
+    for (int32_t a = b; a >= 0; a = t.b_parent[a])
+      for (int32_t j = c.group_ptr_h[a]; j < c.group_ptr_h[a + 1]; ++j) {
+        const SymTerm& sy = c.sym[j];
+        const double core = sy.type == T_FF ? double(sy.kl) * sy.kr : 0.0;
+        by += 8.0 * (double(m) * sy.kl + double(n) * sy.kr + core);
+        fl += 2.0 * n * (core + double(m) * sy.kl);
+      }
+    for (int32_t p = ch.dpptr[k]; p < ch.dpptr[k + 1]; ++p) {
+      const double nr = t.c_size[t.b_sigma[ch.dpairs[2 * p]]];
+      by += 8.0 * (m * nr + nr * n);
+      fl += 2.0 * m * nr * n;
+    }
+    ch.dpos.push_back(i);
+    ch.dby.push_back(by);
+    ch.dfl.push_back(fl);
+  }
+}
 
 void build_chunk(const Ctx& c, Chunk& ch, bool features) {
   const Tree& t = *c.t;
@@ -1163,6 +1239,7 @@ void build_chunk(const Ctx& c, Chunk& ch, bool features) {
   // built here, on the builder's thread while the device runs the previous chunk, rather
   // than at the chunk's first sparse pass, when the device would wait for it
   build_sparse_index(ch);
+  if (ch.near) prepare_direct(c, ch);
 }
 
 void upload_chunk(Chunk& ch, hipStream_t s) {
@@ -1187,6 +1264,19 @@ void upload_chunk(Chunk& ch, hipStream_t s) {
   ch.wsf.alloc(size_t(std::max<int64_t>(ch.tws_f, 1)));
   ch.wst.alloc(size_t(std::max<int64_t>(ch.tws_t, 1)));
   ch.d_td.alloc(ch.blocks.size() + ch.g_leaf.size());
+  if (!ch.dpos.empty()) {
+    std::vector<int32_t> dblk(ch.dpos.size());
+    for (size_t k = 0; k < ch.dpos.size(); ++k) dblk[k] = ch.blocks[size_t(ch.dpos[k])];
+    ch.d_ditems.upload(ch.ditems, s);
+    ch.d_dblk.upload(dblk, s);
+    ch.d_dpptr.upload(ch.dpptr, s);
+    if (ch.dpairs.empty()) {
+      const int32_t none[2] = {0, 0};
+      ch.d_dpairs.upload(none, 2, s);
+    } else {
+      ch.d_dpairs.upload(ch.dpairs, s);
+    }
+  }
   HM_CHECK_HIP(hipStreamSynchronize(s));  // the work-item tables are written by kernels on s
 }
 
@@ -2058,56 +2148,26 @@ void compress_chunk_fixed(Ctx& c, Chunk& ch, FarOut& out) {
 
 // Nearfield targets: S applied to the identity, PW columns at a time, straight into C.
 void evaluate_chunk(Ctx& c, Chunk& ch, double* cpool, const std::vector<int64_t>& coff) {
-  const Tree& t = *c.t;
   const int nt = int(ch.blocks.size());
   // direct kernel: terms and dense x dense pairs of the targets of at most NEAR_MAX x NEAR_MAX,
-  // one work item per 64-row block (the kernel takes its column blocks in turn)
-  std::vector<int32_t> dblk, items;
-  std::vector<int64_t> dco;
-  for (int i = 0; i < nt; ++i) {
-    if (!ch.direct[i]) continue;
-    const int32_t b = ch.blocks[i];
-    const int m = c.m_of(b), n = c.n_of(b);
-    const int k = int32_t(dblk.size());
-    for (int rb = 0; rb < (m + 63) / 64; ++rb) {
-      items.push_back(k);
-      items.push_back(rb << 16);
+  // one work item per 64-row block (the kernel takes its column blocks in turn); its lists
+  // were prepared and uploaded with the chunk
+  const size_t nd = ch.dpos.size();
+  c.st.n_near_direct += int64_t(nd);
+  if (nd) {
+    std::vector<int64_t> dco(nd);
+    for (size_t k = 0; k < nd; ++k) {
+      const int i = ch.dpos[k];
+      dco[k] = coff[size_t(i)];
+      c.st.kern_bytes[K_NEAR] += ch.dby[k];
+      c.st.kern_flops[K_NEAR] += ch.dfl[k];
+      c.charge(ch.blocks[size_t(i)], ch.dby[k], ch.dfl[k]);
     }
-    double by = 8.0 * m * n, fl = 0.0;
-    for (int32_t a = b; a >= 0; a = t.b_parent[a])
-      for (int32_t j = c.group_ptr_h[a]; j < c.group_ptr_h[a + 1]; ++j) {
-        const SymTerm& sy = c.sym[j];
-        const double core = sy.type == T_FF ? double(sy.kl) * sy.kr : 0.0;
-        by += 8.0 * (double(m) * sy.kl + double(n) * sy.kr + core);
-        fl += 2.0 * n * (core + double(m) * sy.kl);
-      }
-    for (int32_t p = ch.dpptr[k]; p < ch.dpptr[k + 1]; ++p) {
-      const double nr = t.c_size[t.b_sigma[ch.dpairs[2 * p]]];
-      by += 8.0 * (m * nr + nr * n);
-      fl += 2.0 * m * nr * n;
-    }
-    dblk.push_back(b);
-    dco.push_back(coff[i]);
-    c.st.kern_bytes[K_NEAR] += by;
-    c.st.kern_flops[K_NEAR] += fl;
-    c.charge(b, by, fl);
-  }
-  c.st.n_near_direct += int64_t(dblk.size());
-  if (!dblk.empty()) {
-    DevBuf<int32_t> d_items, d_blk, d_pptr, d_prs;
-    DevBuf<int64_t> d_co;
-    d_items.upload(items, c.s);
-    d_blk.upload(dblk, c.s);
-    d_co.upload(dco, c.s);
-    d_pptr.upload(ch.dpptr, c.s);
-    std::vector<int32_t> prs = ch.dpairs;
-    if (prs.empty()) prs.push_back(0);
-    d_prs.upload(prs, c.s);
+    ch.d_dco.upload(dco, c.s);
     c.timer.begin(K_NEAR);
-    launch_near_direct(d_items.p, int64_t(items.size() / 2), d_blk.p, d_co.p, d_pptr.p, d_prs.p, c.tv, c.ma, c.mb,
-                       cpool, c.s);
+    launch_near_direct(ch.d_ditems.p, int64_t(ch.ditems.size() / 2), ch.d_dblk.p, ch.d_dco.p, ch.d_dpptr.p,
+                       ch.d_dpairs.p, c.tv, c.ma, c.mb, cpool, c.s);
     c.timer.end();
-    HM_CHECK_HIP(hipStreamSynchronize(c.s));  // the small device arrays above are freed on return
   }
   // identity panels, PW columns at a time: whole targets beyond NEAR_MAX, and the pairs
   // with a subdivided factor of direct targets (added to what the direct kernel wrote)
@@ -2560,6 +2620,14 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     auto prep_batch = [&](int k) {
       const int64_t pos = layout_terms(c, bterms[k]);
       prepare_terms(c, bterms[k], batch_pool.p, pos, preps[k & 1]);
+      // the descriptors go up on the upload stream, so that publishing them is one
+      // device-side scatter (the previous use of these buffers, batch k - 2's scatter,
+      // completed before batch k - 1's targets started)
+      if (s_up.s) {
+        set_current_stream(s_up.s);
+        stage_terms(c, bterms[k], preps[k & 1], s_up.s);
+        set_current_stream(s);  // the calling thread may be the product's own (batch 0)
+      }
     };
     prep_batch(0);
     std::vector<Job> jobs_cur = make_jobs(bnear[0], bfar[0]), jobs_next;
@@ -2568,7 +2636,7 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
       double tc = now_seconds();
       if (next_prep.valid()) next_prep.get();
       execute_terms(c, preps[k & 1], batch_pool.p, c.bpool32);
-      publish_terms(c, bterms[k]);
+      publish_terms(c, bterms[k], &preps[k & 1]);
       c.tv.terms = c.terms.p;
       if (k + 1 < nbatch) {
         if (overlap) next_prep = std::async(std::launch::async, prep_batch, k + 1);
