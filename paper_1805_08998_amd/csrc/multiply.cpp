@@ -15,6 +15,7 @@
 #include <cmath>
 #include <limits>
 #include <cstring>
+#include <deque>
 #include <future>
 #include <map>
 #include <unordered_map>
@@ -2451,7 +2452,9 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     std::vector<int32_t> blocks;
     bool exact = false;  // farfield targets truncated by Algorithm 5
   };
-  auto make_jobs = [&](const std::vector<int32_t>& near, const std::vector<int32_t>& far) {
+  // chunk partition of a batch's targets; reads only the plan, so it may run on another
+  // thread (its time goes to `secs`, not to the shared statistics)
+  auto make_jobs_t = [&](const std::vector<int32_t>& near, const std::vector<int32_t>& far, double* secs) {
     std::vector<Job> jobs;
     const double tp = now_seconds();
     for (auto& p : partition(near, false)) jobs.push_back(Job{false, std::move(p)});
@@ -2462,8 +2465,29 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     const std::vector<int32_t>& rest = opts.o.exact_lowrank ? far_rest : far;
     for (auto& p : partition(far_exact, true)) jobs.push_back(Job{true, std::move(p), true});
     for (auto& p : partition(rest, true)) jobs.push_back(Job{true, std::move(p)});
-    c.st.t_host[2] += now_seconds() - tp;
+    *secs += now_seconds() - tp;
     return jobs;
+  };
+  auto make_jobs = [&](const std::vector<int32_t>& near, const std::vector<int32_t>& far) {
+    double secs = 0;
+    std::vector<Job> jobs = make_jobs_t(near, far, &secs);
+    c.st.t_host[2] += secs;
+    return jobs;
+  };
+  // The next subtree batch's jobs: partitioned on a worker thread while the current batch
+  // runs, and collected when the chunk pipeline first reaches them.
+  struct NextJobs {
+    std::future<std::vector<Job>> f;
+    std::vector<Job> v;
+    double secs = 0;
+    bool ready = true;
+    const std::vector<Job>* get() {
+      if (!ready) {
+        v = f.get();
+        ready = true;
+      }
+      return &v;
+    }
   };
   // the worker builds the next chunk's work lists and uploads them on its own stream
   // while the device runs the current chunk
@@ -2483,8 +2507,12 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     ch->pending = false;
     return ch;
   };
-  // the chunk being built; declared after s_up so that a pending build ends before s_up does
-  std::future<std::unique_ptr<Chunk>> next;
+  // the chunks being built, in job order; declared after s_up so that pending builds end
+  // before s_up does. Two builds run ahead of the device: one build at a time fell behind
+  // it on the heavier chunks (the first nearfield chunk of a subtree batch among them).
+  std::deque<std::future<std::unique_ptr<Chunk>>> pending;
+  const size_t build_depth = overlap ? 2 : 1;
+  size_t carried = 0;  // jobs of the next process_targets call already in `pending`
   auto launch_build = [&](const Job& job) {
     std::unique_ptr<Chunk> ch;
     if (!spare_chunks.empty()) {  // reuse: host arrays keep their capacity
@@ -2499,24 +2527,37 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
     ch->share_s1 = !(job.far && own_inputs);
     const bool features = job.far && collect;
     if (overlap) {
-      next = std::async(std::launch::async, build, std::move(ch), features);
+      pending.push_back(std::async(std::launch::async, build, std::move(ch), features));
     } else {
       std::promise<std::unique_ptr<Chunk>> ready;
       ready.set_value(build_here(std::move(ch), features));
-      next = ready.get_future();
+      pending.push_back(ready.get_future());
     }
   };
-  // Runs the chunks of `jobs`. With `then` (the jobs of the next call), the first chunk of
-  // the next call is built while the last chunk of this one runs; the next call finds it in
-  // `next`. Building reads only the plan, so it may overlap the next subtree batch's term
-  // creation.
-  auto process_targets = [&](const std::vector<Job>& jobs, const std::vector<Job>* then) {
-    if (!jobs.empty() && !next.valid()) launch_build(jobs[0]);
+  // Runs the chunks of `jobs`, keeping `build_depth` chunks in build ahead of the one running.
+  // With `then` (the jobs of the next call), the first chunks of the next call are built
+  // while the last ones of this call run; the next call finds them in `pending`. Building
+  // reads only the plan, so it may overlap the next subtree batch's term creation.
+  auto process_targets = [&](const std::vector<Job>& jobs, NextJobs* then) {
+    size_t launched = std::min(carried, jobs.size()), then_launched = 0;
+    carried = 0;
+    auto top_up = [&]() {
+      while (pending.size() < build_depth) {
+        if (launched < jobs.size()) {
+          launch_build(jobs[launched++]);
+          continue;
+        }
+        const std::vector<Job>* tj = then ? then->get() : nullptr;
+        if (tj && then_launched < tj->size()) launch_build((*tj)[then_launched++]);
+        else break;
+      }
+    };
+    top_up();
     for (size_t k = 0; k < jobs.size(); ++k) {
       const double th = now_seconds();
-      std::unique_ptr<Chunk> chp = next.get();
-      if (k + 1 < jobs.size()) launch_build(jobs[k + 1]);
-      else if (then && !then->empty()) launch_build((*then)[0]);
+      std::unique_ptr<Chunk> chp = pending.front().get();
+      pending.pop_front();
+      top_up();
       Chunk& ch = *chp;
       c.st.t_host[2] += now_seconds() - th;
       if (!jobs[k].far) {
@@ -2563,6 +2604,7 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
       chp->mark_done(s);
       spare_chunks.push_back(std::move(chp));
     }
+    carried = then_launched;
   };
 
   // global terms and targets (levels <= L0)
@@ -2630,7 +2672,8 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
       }
     };
     prep_batch(0);
-    std::vector<Job> jobs_cur = make_jobs(bnear[0], bfar[0]), jobs_next;
+    std::vector<Job> jobs_cur = make_jobs(bnear[0], bfar[0]);
+    NextJobs jobs_next;
     std::future<void> next_prep;
     for (int k = 0; k < nbatch; ++k) {
       double tc = now_seconds();
@@ -2643,10 +2686,21 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
         else prep_batch(k + 1);
       }
       c.st.t_restrict += now_seconds() - tc;
-      if (k + 1 < nbatch) jobs_next = make_jobs(bnear[k + 1], bfar[k + 1]);
-      else jobs_next.clear();
+      jobs_next.v.clear();
+      jobs_next.secs = 0;
+      jobs_next.ready = true;
+      if (k + 1 < nbatch) {
+        if (overlap) {
+          jobs_next.ready = false;
+          jobs_next.f = std::async(std::launch::async, make_jobs_t, std::cref(bnear[k + 1]), std::cref(bfar[k + 1]),
+                                   &jobs_next.secs);
+        } else {
+          jobs_next.v = make_jobs_t(bnear[k + 1], bfar[k + 1], &jobs_next.secs);
+        }
+      }
       process_targets(jobs_cur, overlap ? &jobs_next : nullptr);
-      jobs_cur.swap(jobs_next);
+      jobs_cur = std::move(*jobs_next.get());
+      c.st.t_host[2] += jobs_next.secs;
     }
   }
 
