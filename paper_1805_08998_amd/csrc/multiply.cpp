@@ -2612,25 +2612,35 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   for (int64_t i = 0; i < nsym; ++i)
     if (t->b_level[c.sym[i].child] <= L0) gterms.push_back(int32_t(i));
   DevBuf<double> global_pool;
-  {
-    double tc = now_seconds();
-    CreatePrep gprep;
-    create_terms(c, gterms, global_pool, c.gpool32, gprep);
-    publish_terms(c, gterms);
-    c.tv.terms = c.terms.p;
-    c.st.t_restrict += now_seconds() - tc;
-  }
-  {
-    std::vector<int32_t> nf, ff;
-    for (int32_t b : near_all)
-      if (t->b_level[b] <= L0) nf.push_back(b);
-    for (int32_t b : far_all)
-      if (t->b_level[b] <= L0) ff.push_back(b);
-    process_targets(make_jobs(nf, ff), nullptr);
-  }
-  // batches of deeper subtrees
-  if (L0 < depth) {
-    std::vector<std::vector<int32_t>> bterms(nbatch), bnear(nbatch), bfar(nbatch);
+  // The subtree batches' setup (their term and target lists, the batch pool, batch 0's
+  // preparation and chunk partition) reads only the plan and touches only batch 0's terms:
+  // it runs on a worker thread while the global terms and targets run, and the global
+  // targets' chunk pipeline builds batch 0's first chunks.
+  const bool batches = L0 < depth;
+  std::vector<std::vector<int32_t>> bterms, bnear, bfar;
+  DevBuf<double> batch_pool;
+  // the host part of batch k + 1 (layout, lists, descriptors) is prepared on a worker
+  // thread while batch k's targets run; its creation kernels start once batch k is done,
+  // because both batches use the same pool
+  CreatePrep preps[2];
+  auto prep_batch = [&](int k) {
+    const int64_t pos = layout_terms(c, bterms[k]);
+    prepare_terms(c, bterms[k], batch_pool.p, pos, preps[k & 1]);
+    // the descriptors go up on the upload stream, so that publishing them is one
+    // device-side scatter (the previous use of these buffers, batch k - 2's scatter,
+    // completed before batch k - 1's targets started)
+    if (s_up.s) {
+      set_current_stream(s_up.s);
+      stage_terms(c, bterms[k], preps[k & 1], s_up.s);
+      set_current_stream(s);  // the calling thread may be the product's own
+    }
+  };
+  double setup_alloc_s = 0, setup_jobs_s = 0;  // written by the setup, read after it
+  auto batch_setup = [&]() {
+    set_current_stream(s);
+    bterms.assign(size_t(nbatch), {});
+    bnear.assign(size_t(nbatch), {});
+    bfar.assign(size_t(nbatch), {});
     for (int64_t i = 0; i < nsym; ++i) {
       int32_t ch = c.sym[i].child;
       if (t->b_level[ch] > L0) bterms[batch_of[root0[ch]]].push_back(int32_t(i));
@@ -2646,33 +2656,45 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
       for (int32_t i : bterms[k]) sz += tmem[i] / 8;
       maxpool = std::max(maxpool, sz);
     }
-    DevBuf<double> batch_pool;
-    {
-      const double ta = now_seconds();
-      batch_pool.alloc(size_t(maxpool));
-      // float copies of the batches' terms: one pool of the largest batch's size, so that it
-      // is not reallocated as the batches grow
-      if (c.lowp && c.bpool32.n < size_t(maxpool)) c.bpool32.alloc(size_t(maxpool));
-      c.st.t_host[4] += now_seconds() - ta;
-    }
-    // the host part of batch k + 1 (layout, lists, descriptors) is prepared on a worker
-    // thread while batch k's targets run; its creation kernels start once batch k is done,
-    // because both batches use the same pool
-    CreatePrep preps[2];
-    auto prep_batch = [&](int k) {
-      const int64_t pos = layout_terms(c, bterms[k]);
-      prepare_terms(c, bterms[k], batch_pool.p, pos, preps[k & 1]);
-      // the descriptors go up on the upload stream, so that publishing them is one
-      // device-side scatter (the previous use of these buffers, batch k - 2's scatter,
-      // completed before batch k - 1's targets started)
-      if (s_up.s) {
-        set_current_stream(s_up.s);
-        stage_terms(c, bterms[k], preps[k & 1], s_up.s);
-        set_current_stream(s);  // the calling thread may be the product's own (batch 0)
-      }
-    };
+    const double ta = now_seconds();
+    batch_pool.alloc(size_t(maxpool));
+    // float copies of the batches' terms: one pool of the largest batch's size, so that it
+    // is not reallocated as the batches grow
+    if (c.lowp && c.bpool32.n < size_t(maxpool)) c.bpool32.alloc(size_t(maxpool));
+    setup_alloc_s = now_seconds() - ta;
     prep_batch(0);
-    std::vector<Job> jobs_cur = make_jobs(bnear[0], bfar[0]);
+    return make_jobs_t(bnear[0], bfar[0], &setup_jobs_s);
+  };
+  NextJobs jobs0;
+  if (batches) {
+    if (overlap) {
+      jobs0.ready = false;
+      jobs0.f = std::async(std::launch::async, batch_setup);
+    } else {
+      jobs0.v = batch_setup();
+    }
+  }
+  {
+    double tc = now_seconds();
+    CreatePrep gprep;
+    create_terms(c, gterms, global_pool, c.gpool32, gprep);
+    publish_terms(c, gterms);
+    c.tv.terms = c.terms.p;
+    c.st.t_restrict += now_seconds() - tc;
+  }
+  {
+    std::vector<int32_t> nf, ff;
+    for (int32_t b : near_all)
+      if (t->b_level[b] <= L0) nf.push_back(b);
+    for (int32_t b : far_all)
+      if (t->b_level[b] <= L0) ff.push_back(b);
+    process_targets(make_jobs(nf, ff), batches && overlap ? &jobs0 : nullptr);
+  }
+  // batches of deeper subtrees
+  if (batches) {
+    std::vector<Job> jobs_cur = std::move(*jobs0.get());
+    c.st.t_host[4] += setup_alloc_s;
+    c.st.t_host[2] += setup_jobs_s;
     NextJobs jobs_next;
     std::future<void> next_prep;
     for (int k = 0; k < nbatch; ++k) {
@@ -2702,6 +2724,7 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
       jobs_cur = std::move(*jobs_next.get());
       c.st.t_host[2] += jobs_next.secs;
     }
+    batch_pool.release();  // before C's pool is allocated
   }
 
   // assemble C's pool: nearfield blocks, then farfield chunks
