@@ -231,17 +231,18 @@ def copy_probe():
     for _ in range(4):
         y.copy_(x)
     ev[1].record()
-    s = x.sum()
+    x.sum()
     ev[2].record()
     for _ in range(4):
-        s = x.sum()
+        x.sum()
     ev[3].record()
     torch.cuda.synchronize()
     copy_s = ev[0].elapsed_time(ev[1]) / 1e3 / 4
     read_s = ev[2].elapsed_time(ev[3]) / 1e3 / 4
+    # no device-to-host read of the sum: it would add a small copy kernel to the counters'
+    # calibration, which averages the copy kernel's dispatches
     print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "launches": 5,
-                      "copy_GB_s": 2 * nbytes / copy_s / 1e9, "read_GB_s": nbytes / read_s / 1e9,
-                      "sum_check": float(s) == nbytes // 8}))
+                      "copy_GB_s": 2 * nbytes / copy_s / 1e9, "read_GB_s": nbytes / read_s / 1e9}))
 
 
 def product_source_hash():
