@@ -146,6 +146,96 @@ __global__ void __launch_bounds__(NT) k_probe_residual_w(CTarget* __restrict__ t
   if (lane == 0) T.E2 = e2 / double(g);
 }
 
+// Probe residual of targets above SMALL_M rows, in blocks: the g <= 16 probe columns P are
+// projected against Q = Y[:, :r] (r <= 64) twice, each time as H = Q^T P and P -= Q H on
+// v_mfma_f64_16x16x4f64 (classical Gram-Schmidt on the whole block: the same arithmetic per
+// column as projecting the columns one by one, with Q read four times in all rather than
+// four times per column). Row tiles of 16 go round-robin to the four waves; the waves' partial
+// H are summed in LDS in wave order, so the result does not depend on scheduling.
+// MFMA operand layouts: A[i][k] at lane i + 16k, B[k][j] at lane j + 16k, accumulator
+// register v of lane l holds D[l/16 + 4v][l%16].
+typedef double cdbl4 __attribute__((ext_vector_type(4)));
+static __device__ __forceinline__ cdbl4 cmfma(double a, double b, cdbl4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+constexpr int PBLK_R = 64, PBLK_G = 16;
+
+__global__ void __launch_bounds__(NT) k_probe_residual_blk(CTarget* __restrict__ tg, int nt, int cap, int g) {
+  __shared__ double hp[NT / 64][PBLK_R][PBLK_G];  // per-wave partial H, then H in hp[0]
+  __shared__ double red[NT / 64];
+  CTarget& T = tg[blockIdx.x];
+  if (!T.active || T.m <= SMALL_M) return;
+  const int m = T.m, r = T.r;
+  const double* Q = T.Y;
+  double* P = T.Y + int64_t(cap) * m;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int ntile = (m + 15) >> 4, nrt = (r + 15) >> 4;
+  const bool gok = li < g;
+  const int gc = min(li, g - 1);
+  for (int pass = 0; pass < 2; ++pass) {
+    if (r > 0) {
+      // H_w = Q[rows of wave w]^T P[rows of wave w]: rows are the K dimension
+      cdbl4 acc[PBLK_R / 16];
+#pragma unroll
+      for (int jt = 0; jt < PBLK_R / 16; ++jt) acc[jt] = cdbl4{0.0, 0.0, 0.0, 0.0};
+      for (int t = wv; t < ntile; t += NT / 64) {
+#pragma unroll 1
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int row = 16 * t + 4 * s4 + lk;
+          const bool rok = row < m;
+          const int rc = min(row, m - 1);
+          const double b = rok && gok ? P[int64_t(gc) * m + rc] : 0.0;
+#pragma unroll
+          for (int jt = 0; jt < PBLK_R / 16; ++jt) {
+            if (jt < nrt) {
+              const int j = 16 * jt + li;
+              const double a = rok && j < r ? Q[int64_t(min(j, r - 1)) * m + rc] : 0.0;
+              acc[jt] = cmfma(a, b, acc[jt]);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int jt = 0; jt < PBLK_R / 16; ++jt)
+        if (jt < nrt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) hp[wv][16 * jt + lk + 4 * v][li] = acc[jt][v];
+      __syncthreads();
+      // H = sum of the waves' partials, in wave order
+      for (int e = threadIdx.x; e < 16 * nrt * PBLK_G; e += NT) {
+        const int j = e / PBLK_G, c = e % PBLK_G;
+        double h = 0.0;
+        for (int w = 0; w < NT / 64; ++w) h += hp[w][j][c];
+        hp[0][j][c] = (j < r && c < g) ? h : 0.0;
+      }
+      __syncthreads();
+      // P -= Q H, 16 rows at a time: A = Q[rows, j] (16 consecutive rows per lane group),
+      // B = H[j, c]
+      for (int t = wv; t < ntile; t += NT / 64) {
+        const int row0 = 16 * t;
+        const int rowa = min(row0 + li, m - 1);
+        cdbl4 d = cdbl4{0.0, 0.0, 0.0, 0.0};
+        for (int j0 = 0; j0 < 16 * nrt; j0 += 4) {
+          const int j = j0 + lk;
+          const double a = j < r ? Q[int64_t(min(j, r - 1)) * m + rowa] : 0.0;
+          d = cmfma(a, hp[0][j][li], d);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = row0 + lk + 4 * v;
+          if (row < m && gok) P[int64_t(li) * m + row] -= d[v];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // E2 = sum of the projected probes' squared norms over g
+  double e2 = 0.0;
+  for (int64_t i = threadIdx.x; i < int64_t(g) * m; i += NT) e2 += P[i] * P[i];
+  e2 = block_sum<NT>(e2, red);
+  if (threadIdx.x == 0) T.E2 = e2 / double(g);
+}
+
 // ---------------------------------------------------------------- orthogonalisation
 __global__ void __launch_bounds__(NT) k_orth_append(CTarget* __restrict__ tg, int nt, int src, int cnt,
                                                     int cap) {
@@ -212,7 +302,10 @@ void launch_probe_residual(CTarget* t, int nt, const CParams& p, hipStream_t s) 
   if (p.cap > HMAX) throw Error(HMAT_ERR_INTERNAL, "column capacity above the Gram-Schmidt buffer");
   hipLaunchKernelGGL(k_probe_residual_w, dim3((nt + NT / 64 - 1) / (NT / 64)), dim3(NT), 0, s, t, nt, p.cap, p.g);
   HM_CHECK_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_probe_residual, dim3(nt), dim3(NT), 0, s, t, nt, p.cap, p.g);
+  if (p.g <= PBLK_G && p.cap <= PBLK_R)
+    hipLaunchKernelGGL(k_probe_residual_blk, dim3(nt), dim3(NT), 0, s, t, nt, p.cap, p.g);
+  else
+    hipLaunchKernelGGL(k_probe_residual, dim3(nt), dim3(NT), 0, s, t, nt, p.cap, p.g);
   HM_CHECK_HIP(hipGetLastError());
 }
 
