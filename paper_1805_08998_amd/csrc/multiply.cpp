@@ -2294,13 +2294,15 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   int64_t term_budget;
   {
     // terms of one subtree batch: at most 0.45 of the available memory (shared by the
-    // products in flight) and at most 16 GiB (more batches cost little; very large pools
-    // are slow to map and make the budget depend on what earlier products left in the
-    // block cache)
+    // products in flight; with float copies of the terms, which take half as much again,
+    // two thirds of that) and at most 16 GiB of float64 terms (more batches cost little;
+    // very large pools are slow to map and make the budget depend on what earlier products
+    // left in the block cache)
     const size_t fb = dev_free_bytes() / size_t(std::max(1, opts.concurrency));
+    const double share = c.lowp ? 0.45 * 2.0 / 3.0 : 0.45;
     term_budget = opts.o.workspace_limit > 0 ? 8 * opts.o.workspace_limit
-                                             : std::min<int64_t>(int64_t(0.45 * double(fb)), int64_t(16) << 30);
-    if (c.lowp) term_budget = term_budget / 3 * 2;  // the float copies of the terms take half as much again
+                                             : std::min<int64_t>(int64_t(share * double(fb)), int64_t(16) << 30);
+    if (c.lowp && opts.o.workspace_limit > 0) term_budget = term_budget / 3 * 2;
   }
   const int depth = t->depth;
   std::vector<int64_t> cum(depth + 2, 0);
@@ -2397,10 +2399,10 @@ hmat_status multiply(HMat* A, HMat* B, double eps, const Opts& opts, HMat** Cout
   }
   DevBuf<double> near_buf(size_t(std::max<int64_t>(near_len, 1)));
   // device workspace of one chunk of targets: larger chunks mean fewer, fuller launches
-  // (measured: 3 GiB 6.62 s, 8 GiB 6.37 s, 16 GiB 6.31 s per 262144-point product); two
-  // chunks can be alive at once, so at most 1/16 of the available memory each, shared by
-  // the products in flight (the cache would otherwise overflow and free blocks, and a
-  // device free waits for all streams)
+  // (measured: 3 GiB 6.62 s, 8 GiB 6.37 s, 16 GiB 6.31 s per 262144-point product); three
+  // chunks can be alive at once (one running, two built ahead), so at most 1/16 of the
+  // available memory each, shared by the products in flight (the cache would otherwise
+  // overflow and free blocks, and a device free waits for all streams)
   const int64_t budget = opts.o.workspace_limit > 0
                              ? opts.o.workspace_limit
                              : std::min<int64_t>(int64_t(16) << 30,
