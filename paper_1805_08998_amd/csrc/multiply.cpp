@@ -1315,9 +1315,9 @@ void build_sparse_index(Chunk& ch) {
 }
 
 // One pass over the work items of the active descriptors only (ch.tdx holds the pass's
-// descriptors, already on the device as dtd). Every launched item does what it does in a
-// full pass, so the results are the same bit for bit.
-void run_pass_sparse(Ctx& c, Chunk& ch, const TDesc* dtd, bool trans, bool lowp) {
+// descriptors; they go up in the same copy as the compact lists). Every launched item does
+// what it does in a full pass, so the results are the same bit for bit.
+void run_pass_sparse(Ctx& c, Chunk& ch, bool trans, bool lowp) {
   hipStream_t s = c.s;
   if (!ch.sp_built) build_sparse_index(ch);
   const int32_t nd = int32_t(ch.tdx.size());
@@ -1333,6 +1333,8 @@ void run_pass_sparse(Ctx& c, Chunk& ch, const TDesc* dtd, bool trans, bool lowp)
     h.resize(off + bytes);
     return off;
   };
+  const size_t td_off = section(ch.tdx.size() * sizeof(TDesc));
+  std::memcpy(h.data() + td_off, ch.tdx.data(), ch.tdx.size() * sizeof(TDesc));
   // gathers the active entries of list li from src into a new section; returns (offset, count)
   auto gather = [&](int li, const auto& src) {
     using T = typename std::decay_t<decltype(src)>::value_type;
@@ -1378,6 +1380,7 @@ void run_pass_sparse(Ctx& c, Chunk& ch, const TDesc* dtd, bool trans, bool lowp)
   const auto small4 = gather(8, ch.small4);
   ch.sp_dev.upload(h, s);  // one synchronous copy
   const char* d = ch.sp_dev.p;
+  const TDesc* dtd = reinterpret_cast<const TDesc*>(d + td_off);
   double* ws = trans ? ch.wst.p : ch.wsf.p;
   for (int x = 0; x < 2; ++x) {
     if (cl[x].n == 0) continue;
@@ -1436,8 +1439,6 @@ void run_pass(Ctx& c, Chunk& ch, const std::vector<TDesc>& td, bool trans, bool 
       account(c.st, K_EXPAND, ch.g_exp[g], e.w);
     }
   }
-  ch.d_td.upload(ch.tdx, s);  // synchronous: the descriptors are rewritten for the next pass
-  const TDesc* dtd = ch.d_td.p;
   const int d = trans ? 1 : 0;
   for (size_t i = 0; i < nt; ++i)
     if (td[i].w) {
@@ -1458,9 +1459,11 @@ void run_pass(Ctx& c, Chunk& ch, const std::vector<TDesc>& td, bool trans, bool 
   c.st.n_passes++;
   if (!c.opts.o.full_passes && nact * 8 <= nt && nt >= 64) {
     c.st.n_sparse_passes++;
-    run_pass_sparse(c, ch, dtd, trans, lowp);
+    run_pass_sparse(c, ch, trans, lowp);  // uploads the descriptors with its lists
     return;
   }
+  ch.d_td.upload(ch.tdx, s);  // synchronous: the descriptors are rewritten for the next pass
+  const TDesc* dtd = ch.d_td.p;
   if (!trans) {
     run_tasks(c, ch.t1f, dtd, ch.wsf.p, true, lowp);
     run_tasks(c, ch.t2f, dtd, ch.wsf.p, true, lowp);
