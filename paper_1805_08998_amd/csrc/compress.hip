@@ -554,6 +554,48 @@ void launch_term_columns(CTarget* t, int nt, const TreeView& tv, int c0, int cnt
 }
 
 // ---------------------------------------------------------------- factor output
+// out (rows x k, ld rows) = P (rows x r, ld rows) C[:, :k] with C(j, c) at C[c * r + j],
+// on v_mfma_f64_16x16x4f64: 16-row tiles round-robin over the workgroup's waves, each tile
+// with all (at most four) 16-column blocks of the output, K-steps of 4 over j. Rows at or past
+// `rows`, columns at or past k and steps at or past r are clamped in the loads and masked.
+__device__ __forceinline__ void small_gemm_out(const double* __restrict__ P, const double* __restrict__ C,
+                                               double* __restrict__ out, int rows, int r, int k) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int ntile = (rows + 15) >> 4, nct = (k + 15) >> 4;
+  for (int t = wv; t < ntile; t += NT / 64) {
+    const int row0 = 16 * t;
+    const int ra = min(row0 + li, rows - 1);
+    cdbl4 d[CAPMAX_CORE / 16];
+#pragma unroll
+    for (int ct = 0; ct < CAPMAX_CORE / 16; ++ct) d[ct] = cdbl4{0.0, 0.0, 0.0, 0.0};
+    for (int j0 = 0; j0 < r; j0 += 4) {
+      const int j = j0 + lk;
+      const bool jok = j < r;
+      const int jc = min(j, r - 1);
+      const double a = jok && row0 + li < rows ? P[int64_t(jc) * rows + ra] : 0.0;
+#pragma unroll
+      for (int ct = 0; ct < CAPMAX_CORE / 16; ++ct) {
+        if (ct < nct) {
+          const int c = 16 * ct + li;
+          const double b = jok && c < k ? C[min(c, k - 1) * r + jc] : 0.0;
+          d[ct] = cmfma(a, b, d[ct]);
+        }
+      }
+    }
+#pragma unroll
+    for (int ct = 0; ct < CAPMAX_CORE / 16; ++ct) {
+      if (ct < nct) {
+        const int c = 16 * ct + li;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = row0 + lk + 4 * v;
+          if (row < rows && c < k) out[int64_t(c) * rows + row] = d[ct][v];
+        }
+      }
+    }
+  }
+}
+
 __global__ void __launch_bounds__(NT) k_write_factors(const CTarget* __restrict__ tg, int nt, int cap,
                                                       double* __restrict__ pool) {
   const CTarget& T = tg[blockIdx.x];
@@ -563,21 +605,8 @@ __global__ void __launch_bounds__(NT) k_write_factors(const CTarget* __restrict_
   const double* J = T.core + cap * cap;
   double* L = pool + T.out_off;
   double* R = L + int64_t(m) * k;
-  // rows of both outputs are independent: one thread per row, k columns
-  for (int i = threadIdx.x; i < m; i += NT) {
-    for (int c = 0; c < k; ++c) {
-      double acc = 0.0;
-      for (int j = 0; j < r; ++j) acc += T.Y[int64_t(j) * m + i] * W[c * r + j];
-      L[int64_t(c) * m + i] = acc;
-    }
-  }
-  for (int i = threadIdx.x; i < n; i += NT) {
-    for (int c = 0; c < k; ++c) {
-      double acc = 0.0;
-      for (int j = 0; j < r; ++j) acc += T.Z[int64_t(j) * n + i] * J[c * r + j];
-      R[int64_t(c) * n + i] = acc;
-    }
-  }
+  small_gemm_out(T.Y, W, L, m, r, k);  // L = Q W
+  small_gemm_out(T.Z, J, R, n, r, k);  // R = Q_Z J
 }
 
 void launch_write_factors(CTarget* t, int nt, const CParams& p, double* pool, hipStream_t s) {
