@@ -342,10 +342,115 @@ void launch_check(CTarget* t, int nt, const CParams& p, int32_t* pending, hipStr
 // ---------------------------------------------------------------- core SVD + truncation
 constexpr int CAPMAX = 64;
 
+// One-sided Jacobi SVD of the r x r matrix M (columns of stride LD, in LDS) by one wave
+// (lane 0..63): the rotations accumulate in J; then the column norms sigma, their descending
+// order and the truncation rank k (T.k, T.nB2 and T.svd_capped, from lane 0). The pairs are
+// taken in parallel (round-robin) order: a sweep is nr - 1 rounds of nr / 2 disjoint pairs
+// (nr = r rounded up to even; pairs with the padding index are skipped), and each pair is
+// rotated by a group of G lanes at once. A group's rotation angle is taken from its first
+// lane, so the lanes of a group apply the same rotation.
+__device__ void core_jacobi_wave(CTarget& T, double* M, double* J, double* sig, int* order, int r, int LD,
+                                 double eps, double kappa, int lane) {
+  for (int i = 0; i < r; ++i)
+    if (lane < r) J[i * LD + lane] = (lane == i) ? 1.0 : 0.0;
+  const int nr = (r + 1) & ~1;
+  int npair = 1;
+  while (npair < nr / 2) npair <<= 1;         // groups: a power of two, at most 32
+  const int G = 64 / npair;                   // lanes per group
+  const int grp = lane / G, gl = lane % G;    // group and lane within it
+  const int leader = grp * G;
+  int capped = 1;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    int rotated = 0;
+    for (int t = 0; t + 1 < nr; ++t) {
+      // round t of the circle schedule: position 0 holds index 0, position k >= 1 holds
+      // 1 + (k - 1 + t) mod (nr - 1); pair k joins positions k and nr - 1 - k
+      int p = -1, q = -1;
+      if (grp < nr / 2) {
+        const int k0 = grp, k1 = nr - 1 - grp;
+        const int i0 = k0 == 0 ? 0 : 1 + (k0 - 1 + t) % (nr - 1);
+        const int i1 = 1 + (k1 - 1 + t) % (nr - 1);
+        p = min(i0, i1);
+        q = max(i0, i1);
+      }
+      const bool live = p >= 0 && q < r;
+      double a = 0.0, b = 0.0, c = 0.0;
+      if (live)
+        for (int e = gl; e < r; e += G) {
+          const double mp = M[p * LD + e], mq = M[q * LD + e];
+          a += mp * mp;
+          b += mq * mq;
+          c += mp * mq;
+        }
+      for (int o = 1; o < G; o <<= 1) {  // within the group (G divides 64, groups aligned)
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+        c += __shfl_xor(c, o, 64);
+      }
+      a = __shfl(a, leader, 64);
+      b = __shfl(b, leader, 64);
+      c = __shfl(c, leader, 64);
+      const bool rot = live && !(fabs(c) <= 1e-15 * sqrt(a * b) || c == 0.0);
+      if (rot) {
+        const double zeta = (b - a) / (2.0 * c);
+        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+        for (int e = gl; e < r; e += G) {
+          const double mp = M[p * LD + e], mq = M[q * LD + e];
+          M[p * LD + e] = cs * mp - sn * mq;
+          M[q * LD + e] = sn * mp + cs * mq;
+          const double jp = J[p * LD + e], jq = J[q * LD + e];
+          J[p * LD + e] = cs * jp - sn * jq;
+          J[q * LD + e] = sn * jp + cs * jq;
+        }
+      }
+      rotated |= __ballot(rot) != 0 ? 1 : 0;
+      // the next round reads columns other groups wrote: keep the LDS accesses in order
+      // (one wave: its LDS instructions complete in issue order)
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (!rotated) {
+      capped = 0;
+      break;
+    }
+  }
+  if (lane == 0) T.svd_capped = capped;
+  for (int j = 0; j < r; ++j) {
+    double mj = lane < r ? M[j * LD + lane] : 0.0;
+    double s2 = wave_sum(mj * mj);
+    if (lane == 0) sig[j] = sqrt(s2);
+  }
+  if (lane == 0) {
+    for (int j = 0; j < r; ++j) order[j] = j;
+    for (int a = 1; a < r; ++a) {  // insertion sort, descending
+      int x = order[a];
+      int b = a - 1;
+      while (b >= 0 && sig[order[b]] < sig[x]) {
+        order[b + 1] = order[b];
+        --b;
+      }
+      order[b + 1] = x;
+    }
+    double total = 0.0;
+    for (int j = 0; j < r; ++j) total += sig[j] * sig[j];
+    double thr = eps * eps * (total + T.E2) - kappa * T.E2;
+    int k = r;
+    double tail = 0.0;  // tail(k) = sum_{i >= k} sigma_i^2 in sorted order
+    for (int kk = r; kk >= 0; --kk) {
+      if (kk < r) tail += sig[order[kk]] * sig[order[kk]];
+      if (tail <= thr) k = kk;
+      else break;
+    }
+    T.k = k;
+    T.nB2 = total;
+  }
+}
+
 // LD (<= CAPMAX) is the largest column count rz of the launch's targets: the two LD x LD
 // work arrays live in dynamic LDS, so small cores leave room for more workgroups per CU.
 __global__ void __launch_bounds__(NT) k_core(CTarget* __restrict__ tg, int nt, int cap, double eps,
-                                             double kappa, int LD) {
+                                             double kappa, int LD, int skip_n, int skip_r) {
   __shared__ double h[CAPMAX];
   __shared__ double red[NT / 64];
   extern __shared__ double dyn[];
@@ -354,6 +459,7 @@ __global__ void __launch_bounds__(NT) k_core(CTarget* __restrict__ tg, int nt, i
   __shared__ double sig[CAPMAX];
   __shared__ int order[CAPMAX];
   CTarget& T = tg[blockIdx.x];
+  if (T.n <= skip_n && T.rz <= skip_r) return;  // done by k_core_w
   const int n = T.n, r = min(T.rz, LD);  // the host sizes LD as the maximum rz
   double* Z = T.Z;
   for (int i = threadIdx.x; i < LD * LD; i += NT) {
@@ -379,108 +485,8 @@ __global__ void __launch_bounds__(NT) k_core(CTarget* __restrict__ tg, int nt, i
     if (threadIdx.x == 0) M[j * LD + j] = d;
     __syncthreads();
   }
-  // One-sided Jacobi on the columns of M (r x r), accumulating J; wave 0 only. The pairs
-  // are taken in parallel (round-robin) order: a sweep is nr - 1 rounds of nr / 2 disjoint
-  // pairs (nr = r rounded up to even; pairs with the padding index are skipped), and each
-  // pair is rotated by a group of G lanes at once. A group's rotation angle is taken from
-  // its first lane, so the lanes of a group apply the same rotation.
-  if (threadIdx.x < 64) {
-    const int lane = threadIdx.x;
-    for (int i = 0; i < r; ++i)
-      if (lane < r) J[i * LD + lane] = (lane == i) ? 1.0 : 0.0;
-    const int nr = (r + 1) & ~1;
-    int npair = 1;
-    while (npair < nr / 2) npair <<= 1;         // groups: a power of two, at most 32
-    const int G = 64 / npair;                   // lanes per group
-    const int grp = lane / G, gl = lane % G;    // group and lane within it
-    const int leader = grp * G;
-    int capped = 1;
-    for (int sweep = 0; sweep < 60; ++sweep) {
-      int rotated = 0;
-      for (int t = 0; t + 1 < nr; ++t) {
-        // round t of the circle schedule: position 0 holds index 0, position k >= 1 holds
-        // 1 + (k - 1 + t) mod (nr - 1); pair k joins positions k and nr - 1 - k
-        int p = -1, q = -1;
-        if (grp < nr / 2) {
-          const int k0 = grp, k1 = nr - 1 - grp;
-          const int i0 = k0 == 0 ? 0 : 1 + (k0 - 1 + t) % (nr - 1);
-          const int i1 = 1 + (k1 - 1 + t) % (nr - 1);
-          p = min(i0, i1);
-          q = max(i0, i1);
-        }
-        const bool live = p >= 0 && q < r;
-        double a = 0.0, b = 0.0, c = 0.0;
-        if (live)
-          for (int e = gl; e < r; e += G) {
-            const double mp = M[p * LD + e], mq = M[q * LD + e];
-            a += mp * mp;
-            b += mq * mq;
-            c += mp * mq;
-          }
-        for (int o = 1; o < G; o <<= 1) {  // within the group (G divides 64, groups aligned)
-          a += __shfl_xor(a, o, 64);
-          b += __shfl_xor(b, o, 64);
-          c += __shfl_xor(c, o, 64);
-        }
-        a = __shfl(a, leader, 64);
-        b = __shfl(b, leader, 64);
-        c = __shfl(c, leader, 64);
-        const bool rot = live && !(fabs(c) <= 1e-15 * sqrt(a * b) || c == 0.0);
-        if (rot) {
-          const double zeta = (b - a) / (2.0 * c);
-          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-          for (int e = gl; e < r; e += G) {
-            const double mp = M[p * LD + e], mq = M[q * LD + e];
-            M[p * LD + e] = cs * mp - sn * mq;
-            M[q * LD + e] = sn * mp + cs * mq;
-            const double jp = J[p * LD + e], jq = J[q * LD + e];
-            J[p * LD + e] = cs * jp - sn * jq;
-            J[q * LD + e] = sn * jp + cs * jq;
-          }
-        }
-        rotated |= __ballot(rot) != 0 ? 1 : 0;
-        // the next round reads columns other groups wrote: keep the LDS accesses in order
-        // (one wave: its LDS instructions complete in issue order)
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        __builtin_amdgcn_wave_barrier();
-      }
-      if (!rotated) {
-        capped = 0;
-        break;
-      }
-    }
-    if (lane == 0) T.svd_capped = capped;
-    for (int j = 0; j < r; ++j) {
-      double mj = lane < r ? M[j * LD + lane] : 0.0;
-      double s2 = wave_sum(mj * mj);
-      if (lane == 0) sig[j] = sqrt(s2);
-    }
-    if (lane == 0) {
-      for (int j = 0; j < r; ++j) order[j] = j;
-      for (int a = 1; a < r; ++a) {  // insertion sort, descending
-        int x = order[a];
-        int b = a - 1;
-        while (b >= 0 && sig[order[b]] < sig[x]) {
-          order[b + 1] = order[b];
-          --b;
-        }
-        order[b + 1] = x;
-      }
-      double total = 0.0;
-      for (int j = 0; j < r; ++j) total += sig[j] * sig[j];
-      double thr = eps * eps * (total + T.E2) - kappa * T.E2;
-      int k = r;
-      double tail = 0.0;  // tail(k) = sum_{i >= k} sigma_i^2 in sorted order
-      for (int kk = r; kk >= 0; --kk) {
-        if (kk < r) tail += sig[order[kk]] * sig[order[kk]];
-        if (tail <= thr) k = kk;
-        else break;
-      }
-      T.k = k;
-      T.nB2 = total;
-    }
-  }
+  // One-sided Jacobi on the columns of M (r x r), accumulating J; wave 0 only
+  if (threadIdx.x < 64) core_jacobi_wave(T, M, J, sig, order, r, LD, eps, kappa, threadIdx.x);
   __syncthreads();
   // store the sorted W (= M) and J columns plus sigma in core
   double* core = T.core;
@@ -493,12 +499,94 @@ __global__ void __launch_bounds__(NT) k_core(CTarget* __restrict__ tg, int nt, i
   for (int j = threadIdx.x; j < r; j += NT) core[2 * cap * cap + j] = sig[order[j]];
 }
 
+// k_core for targets whose Z has at most SMALL_M rows and at most LD (<= CORE_W_LD) columns:
+// one wave per target (four per workgroup), lane l owning rows l and l + 64 of Z, so the QR
+// of Z needs wave sums only; then the same Jacobi stage. Each wave's LDS: M and J (LD x LD
+// each), sigma (64), the coefficients of the current column (64) and the sort order (64 ints).
+// k_core takes the other targets of the launch.
+constexpr int CORE_W_LD = 24;  // four waves of LDS stay within 64 KiB per workgroup
+__host__ __device__ constexpr int core_w_lds(int LD) { return 2 * LD * LD + 64 + 64 + 32; }  // doubles
+
+__global__ void __launch_bounds__(NT) k_core_w(CTarget* __restrict__ tg, int nt, int cap, double eps, double kappa,
+                                               int LD) {
+  extern __shared__ double dyn[];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t = blockIdx.x * (NT / 64) + wv;
+  if (t >= nt) return;
+  CTarget& T = tg[t];
+  if (T.n > SMALL_M || T.rz > LD) return;
+  double* M = dyn + wv * core_w_lds(LD);
+  double* J = M + LD * LD;
+  double* sig = J + LD * LD;
+  double* hs = sig + 64;
+  int* order = reinterpret_cast<int*>(hs + 64);
+  const int n = T.n, r = min(T.rz, LD);
+  double* Z = T.Z;
+  for (int i = lane; i < LD * LD; i += 64) {
+    M[i] = 0.0;
+    J[i] = 0.0;
+  }
+  const bool in0 = lane < n, in1 = lane + 64 < n;
+  // CGS2 QR of Z (n x r) in place; R(i, j) goes to M(j, i)
+  for (int j = 0; j < r; ++j) {
+    double* v = Z + int64_t(j) * n;
+    double v0 = in0 ? v[lane] : 0.0, v1 = in1 ? v[lane + 64] : 0.0;
+    const double n0 = wave_uniform(wave_sum(v0 * v0 + v1 * v1));
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i = 0; i < j; ++i) {
+        const double* q = Z + int64_t(i) * n;
+        const double h = wave_uniform(wave_sum((in0 ? q[lane] : 0.0) * v0 + (in1 ? q[lane + 64] : 0.0) * v1));
+        if (lane == 0) {
+          hs[i] = h;
+          M[i * LD + j] += h;  // M(j, i) = R(i, j)
+        }
+      }
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      __builtin_amdgcn_wave_barrier();
+      for (int i = 0; i < j; ++i) {
+        const double* q = Z + int64_t(i) * n;
+        const double h = hs[i];
+        if (in0) v0 -= q[lane] * h;
+        if (in1) v1 -= q[lane + 64] * h;
+      }
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      __builtin_amdgcn_wave_barrier();
+    }
+    const double n1 = wave_uniform(wave_sum(v0 * v0 + v1 * v1));
+    const bool keep = n1 > 0.0 && n1 > 1e-28 * n0;
+    const double d = keep ? sqrt(n1) : 0.0;
+    const double inv = keep ? 1.0 / d : 0.0;
+    if (in0) v[lane] = v0 * inv;
+    if (in1) v[lane + 64] = v1 * inv;
+    if (lane == 0) M[j * LD + j] = d;
+  }
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_wave_barrier();
+  core_jacobi_wave(T, M, J, sig, order, r, LD, eps, kappa, lane);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_wave_barrier();
+  // store the sorted W (= M) and J columns plus sigma in core
+  double* core = T.core;
+  for (int idx = lane; idx < r * r; idx += 64) {
+    const int jj = idx / r, i = idx % r;
+    const int src = order[jj];
+    core[idx] = M[src * LD + i];
+    core[cap * cap + idx] = J[src * LD + i];
+  }
+  for (int jj = lane; jj < r; jj += 64) core[2 * cap * cap + jj] = sig[order[jj]];
+}
+
 void launch_core(CTarget* t, int nt, const CParams& p, hipStream_t s, int rmax) {
   if (nt <= 0) return;
   if (p.cap > CAPMAX) throw Error(HMAT_ERR_INTERNAL, "column capacity above 64");
   const int ld = std::max(1, std::min(rmax > 0 ? rmax : p.cap, CAPMAX));
+  // small targets (n <= SMALL_M, rz <= ldw) in one wave each, the others in k_core
+  const int ldw = std::min(ld, CORE_W_LD);
+  hipLaunchKernelGGL(k_core_w, dim3((nt + NT / 64 - 1) / (NT / 64)), dim3(NT),
+                     size_t(NT / 64) * core_w_lds(ldw) * sizeof(double), s, t, nt, p.cap, p.eps, p.kappa, ldw);
+  HM_CHECK_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_core, dim3(nt), dim3(NT), size_t(2) * ld * ld * sizeof(double), s, t, nt, p.cap, p.eps,
-                     p.kappa, ld);
+                     p.kappa, ld, SMALL_M, ldw);
   HM_CHECK_HIP(hipGetLastError());
 }
 
