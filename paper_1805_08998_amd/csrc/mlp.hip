@@ -159,12 +159,13 @@ static void forward(RankModel& M, Work& W, const float* F, int n, hipStream_t s)
   HM_CHECK_HIP(hipGetLastError());
 }
 
-// gradient of the mean squared error over n samples into M.g; returns nothing (se holds errors)
-static void backward(RankModel& M, Work& W, const float* ranks, int n, hipStream_t s) {
+// gradient of the mean squared error over n samples into M.g; the samples' squared errors
+// go to se
+static void backward(RankModel& M, Work& W, const float* ranks, int n, float* se, hipStream_t s) {
   const float* P = M.p.p;
   float* G = M.g.p;
   const float sc = 1.f / float(n);
-  hipLaunchKernelGGL(k_mse, dim3(nblk(n)), dim3(256), 0, s, W.O.p, ranks, n, W.normd.p, W.dO.p, W.se.p);
+  hipLaunchKernelGGL(k_mse, dim3(nblk(n)), dim3(256), 0, s, W.O.p, ranks, n, W.normd.p, W.dO.p, se);
   hipLaunchKernelGGL(k_dense_bwd_w, dim3(wblk(NH + 1)), dim3(256), 0, s, W.dO.p, n, 1, W.H3.p, NH, sc, G + OFF_W4,
                      G + OFF_B4);
   hipLaunchKernelGGL(k_dense_bwd_x, dim3(nblk(int64_t(n) * NH)), dim3(256), 0, s, W.dO.p, n, 1, P + OFF_W4, NH, W.H3.p,
@@ -312,7 +313,7 @@ hmat_status hmat_rank_model_grad(hmat_rank_model m, const float* feats, const fl
   F.upload(feats, size_t(n) * NF, s);
   R.upload(ranks, size_t(n), s);
   forward(M, W, F.p, int(n), s);
-  backward(M, W, R.p, int(n), s);
+  backward(M, W, R.p, int(n), W.se.p, s);
   std::vector<float> se(n);
   HM_CHECK_HIP(hipMemcpy(grads, M.g.p, 4 * NPARAM, hipMemcpyDeviceToHost));
   HM_CHECK_HIP(hipMemcpy(se.data(), W.se.p, 4 * n, hipMemcpyDeviceToHost));
@@ -357,43 +358,45 @@ hmat_status hmat_rank_model_train(hmat_rank_model m, const float* feats, const f
   Work W;
   W.ensure(B);
   W.normd.upload(M.norm, s);
-  DevBuf<float> Fall, Rall;
-  Fall.upload(feats, size_t(n) * NF, s);
-  Rall.upload(ranks, size_t(n), s);
-  // shuffled minibatches, gathered on the host into pinned order (deterministic for a seed)
+  // Shuffled minibatches (deterministic for a seed): an epoch's samples are gathered on the
+  // host in shuffled order and uploaded once, and its per-sample squared errors are read back
+  // once, so the minibatches' launches run back to back with no synchronisation between them.
   std::mt19937_64 rng(o.seed);
   std::vector<int64_t> perm(n);
   for (int64_t i = 0; i < n; ++i) perm[i] = i;
-  std::vector<float> fb(size_t(B) * NF), rb(B), se(B);
-  DevBuf<float> Fb(size_t(B) * NF), Rb(B);
+  const size_t ns = static_cast<size_t>(n);
+  std::vector<float> fe(ns * NF), re(ns), see(ns);
+  DevBuf<float> Fe(ns * NF), Re(ns), Se(ns);
   const float b1 = 0.9f, b2 = 0.999f;
   for (int ep = 0; ep < o.epochs; ++ep) {
     std::shuffle(perm.begin(), perm.end(), rng);
-    double ep_loss = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      std::memcpy(&fe[size_t(i) * NF], feats + perm[i] * NF, 4 * NF);
+      re[size_t(i)] = ranks[perm[i]];
+    }
+    // synchronous copies: the previous epoch's kernels, which read these buffers, come
+    // before them on the stream
+    Fe.upload(fe.data(), size_t(n) * NF, s);
+    Re.upload(re.data(), size_t(n), s);
     int64_t ep_cnt = 0;
     for (int64_t st = 0; st + B <= n || (st < n && st == 0); st += B) {
       const int nb = int(std::min<int64_t>(B, n - st));
-      for (int i = 0; i < nb; ++i) {
-        std::memcpy(&fb[size_t(i) * NF], feats + perm[st + i] * NF, 4 * NF);
-        rb[i] = ranks[perm[st + i]];
-      }
-      Fb.upload(fb.data(), size_t(nb) * NF, s);
-      Rb.upload(rb.data(), size_t(nb), s);
-      forward(M, W, Fb.p, nb, s);
-      backward(M, W, Rb.p, nb, s);
+      forward(M, W, Fe.p + st * NF, nb, s);
+      backward(M, W, Re.p + st, nb, Se.p + st, s);
       ++M.step;
       const float c1 = 1.f - std::pow(b1, float(M.step)), c2 = 1.f - std::pow(b2, float(M.step));
       hipLaunchKernelGGL(k_adam, dim3(nblk(NPARAM)), dim3(256), 0, s, M.p.p, M.m.p, M.v.p, M.g.p, NPARAM, o.lr, b1,
                          b2, c1, c2, o.weight_decay);
       HM_CHECK_HIP(hipGetLastError());
-      if (o.loss_out) {
-        HM_CHECK_HIP(hipMemcpyAsync(se.data(), W.se.p, 4 * nb, hipMemcpyDeviceToHost, s));
-        HM_CHECK_HIP(hipStreamSynchronize(s));
-        for (int i = 0; i < nb; ++i) ep_loss += se[i];
-        ep_cnt += nb;
-      }
+      ep_cnt += nb;
     }
-    if (o.loss_out) o.loss_out[ep] = float(ep_loss / double(std::max<int64_t>(ep_cnt, 1)));
+    if (o.loss_out) {
+      HM_CHECK_HIP(hipMemcpyAsync(see.data(), Se.p, 4 * size_t(ep_cnt), hipMemcpyDeviceToHost, s));
+      HM_CHECK_HIP(hipStreamSynchronize(s));
+      double ep_loss = 0;
+      for (int64_t i = 0; i < ep_cnt; ++i) ep_loss += see[size_t(i)];  // minibatch order, as they ran
+      o.loss_out[ep] = float(ep_loss / double(std::max<int64_t>(ep_cnt, 1)));
+    }
   }
   HM_CHECK_HIP(hipStreamSynchronize(s));
   API_END
